@@ -1,0 +1,422 @@
+/*
+ * kappa_oracle.c -- FP64 CPU oracle of the approximate Kappa velocity sampler
+ * of Zenitani & Umeda, "An approximate Kappa generator for particle
+ * simulations" (arXiv 2602.05606).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code with the HIP library: its Philox, uniform maps, parameter
+ * setup, digamma and inversion are written here from the published
+ * definitions, and nothing here is used by the product path.
+ *
+ * Citations name the paper's sections, its LaTeX equation labels (eq:...)
+ * and Table 1 (label table:kappa).
+ *
+ * Everything is FP64 and uses the C library's log, log1p, exp, expm1, sqrt,
+ * sin and cos.  Compile with -O2 -ffp-contract=off and without fast-math.
+ *
+ * Parity pins: every function here is pinned by a CPU test (limits of a and
+ * b/c, asymptotic matching against the exact Beta-prime CDF, the G round
+ * trip, the KS test against the exact CDF, the paper's statements on the
+ * relative entropy and the energy error, finite differences of the adjoint,
+ * and Philox against an independent library implementation).  None is
+ * "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition: Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11.  Ten rounds; each
+ * round multiplies counter words 0 and 2 by two fixed 32-bit multipliers,
+ * and the key is advanced by the two Weyl constants between rounds.        */
+/* ------------------------------------------------------------------------ */
+
+#define PHILOX_MUL_A 0xD2511F53u
+#define PHILOX_MUL_B 0xCD9E8D57u
+#define PHILOX_WEYL_A 0x9E3779B9u
+#define PHILOX_WEYL_B 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_WEYL_A;
+            k1 += PHILOX_WEYL_B;
+        }
+        uint64_t prod_a = (uint64_t)PHILOX_MUL_A * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)PHILOX_MUL_B * (uint64_t)x2;
+        uint32_t hi_a = (uint32_t)(prod_a >> 32), lo_a = (uint32_t)prod_a;
+        uint32_t hi_b = (uint32_t)(prod_b >> 32), lo_b = (uint32_t)prod_b;
+        uint32_t y0 = hi_b ^ x1 ^ k0;
+        uint32_t y1 = lo_b;
+        uint32_t y2 = hi_a ^ x3 ^ k1;
+        uint32_t y3 = lo_a;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The block drawn for particle i of segment seg, draw d:
+ * counter = (low word of i, high word of i, seg, d), key = (low, high word of seed). */
+static void particle_block(uint64_t seed, uint64_t i, uint32_t seg, uint32_t draw, uint32_t r[4])
+{
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), seg, draw};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, r);
+}
+
+void oracle_philox_blocks(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg,
+                          uint32_t draw, uint32_t *out)
+{
+    for (uint64_t j = 0; j < n; ++j)
+        particle_block(seed, counter_offset + j, seg, draw, out + 4 * j);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Digamma, needed only for the derivative of the setup parameters with
+ * respect to kappa.  Recurrence psi(x) = psi(x+1) - 1/x up to x >= 12, then
+ * the standard asymptotic series psi(x) ~ ln x - 1/(2x) - sum B_2k/(2k x^2k)
+ * (Abramowitz & Stegun 6.3.5 and 6.3.18).                                  */
+/* ------------------------------------------------------------------------ */
+double oracle_digamma(double x)
+{
+    double shift = 0.0;
+    while (x < 12.0) {
+        shift -= 1.0 / x;
+        x += 1.0;
+    }
+    double inv = 1.0 / x, inv2 = inv * inv;
+    /* Bernoulli numbers B2..B12 divided by 2k */
+    double series = inv2 * (1.0 / 12.0 - inv2 * (1.0 / 120.0 - inv2 * (1.0 / 252.0 -
+                    inv2 * (1.0 / 240.0 - inv2 * (1.0 / 132.0 - inv2 * (691.0 / 32760.0))))));
+    return shift + log(x) - 0.5 * inv - series;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-species setup (Table 1, first four rows, "required only once").      */
+/*   kappa* = kappa - 1/2                                      (eq:k2)      */
+/*   a = (1/kappa) * (2 / (3 B(3/2, kappa*)))^(2/3)            (eq:a)       */
+/*   c = (0.123 k^2 - 1.12 k + 2.56) / (k^2 - 7.89 k + 15.6)   (eq:c)       */
+/*   b = {kappa* (3/2) B(3/2, kappa*)}^(1/kappa*) (kappa* / kappa) c  (eq:b)  */
+/* with B(x, y) = Gamma(x) Gamma(y) / Gamma(x + y) (Sec. 6).                */
+/* Also the kappa-derivatives of a, b, c used by the adjoint.               */
+/* ------------------------------------------------------------------------ */
+
+enum {
+    OP_KSTAR = 0, OP_A, OP_B, OP_C, OP_B_OVER_C, OP_DA, OP_DB, OP_DC, OP_LNBETA, OP_COUNT
+};
+
+void oracle_params(double kappa, double *p)
+{
+    double ks = kappa - 0.5;
+    double lnB = lgamma(1.5) + lgamma(ks) - lgamma(kappa + 1.0);
+    double a = (1.0 / kappa) * pow(2.0 / (3.0 * exp(lnB)), 2.0 / 3.0);
+    double cn = 0.123 * kappa * kappa - 1.12 * kappa + 2.56;
+    double cd = kappa * kappa - 7.89 * kappa + 15.6;
+    double c = cn / cd;
+    double ln_inner = log(ks * 1.5) + lnB; /* ln{kappa* (3/2) B} */
+    double b_over_c = exp(ln_inner / ks) * ks / kappa;
+    double b = b_over_c * c;
+
+    /* d lnB / d kappa = psi(kappa*) - psi(kappa + 1) */
+    double dlnB = oracle_digamma(ks) - oracle_digamma(kappa + 1.0);
+    double da = a * (-1.0 / kappa - (2.0 / 3.0) * dlnB);
+    double dcn = 0.246 * kappa - 1.12, dcd = 2.0 * kappa - 7.89;
+    double dc = (dcn * cd - cn * dcd) / (cd * cd);
+    double dln_boc = -ln_inner / (ks * ks) + (1.0 / ks) * (1.0 / ks + dlnB) + 1.0 / ks - 1.0 / kappa;
+    double db = b * dln_boc + b_over_c * dc;
+
+    p[OP_KSTAR] = ks;
+    p[OP_A] = a;
+    p[OP_B] = b;
+    p[OP_C] = c;
+    p[OP_B_OVER_C] = b_over_c;
+    p[OP_DA] = da;
+    p[OP_DB] = db;
+    p[OP_DC] = dc;
+    p[OP_LNBETA] = lnB;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Uniform maps.  The paper draws U1, U2, U3 ~ Uniform(0,1) (Table 1) and
+ * warns against a zero uniform (Sec. 6).  Reading used here: open midpoint
+ * dyadics, with U1 carried as (side, small value) so that both U1 and 1-U1
+ * are exact.
+ *   mode 0 (FP64): m = top 53 bits of (r0:r3).  m < 2^52: U1 = (2m+1) 2^-54
+ *                  on the low side; else W1 = 1 - U1 = (2^54-2m-1) 2^-54.
+ *                  U2 = (r1 + 1/2) 2^-32, U3 = (r2 + 1/2) 2^-32.
+ *   mode 1 (FP32 bulk, FP64 tail): m24 = r0 >> 8, same map with 24 bits;
+ *                  if m24 >= 2^24 - 16 (W1 < 2^-20) the FP64 W1 of mode 0
+ *                  is used instead.  U2, U3 from the top 24 bits of r1, r2.
+ *   mode 2: mode 1 without the tail refinement (diagnostics).              */
+/* ------------------------------------------------------------------------ */
+
+enum { SIDE_LOW = 0, SIDE_HIGH = 1 };
+enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_NOTAIL = 2 };
+
+/* Returns 1 when the FP64 tail refinement was taken. */
+int oracle_speed_uniform(int mode, uint32_t r0, uint32_t r3, int *side, double *u)
+{
+    uint64_t m53 = ((((uint64_t)r0) << 32) | (uint64_t)r3) >> 11;
+    uint32_t m24 = r0 >> 8;
+    int use53 = (mode == MODE_FP64);
+    int tail = 0;
+    if (mode != MODE_FP64 && m24 >= (1u << 24) - 16u) {
+        tail = (mode == MODE_FP32);
+        use53 = tail;
+    }
+    if (use53) {
+        if (m53 < (1ull << 52)) {
+            *side = SIDE_LOW;
+            *u = ldexp((double)(2 * m53 + 1), -54);
+        } else {
+            *side = SIDE_HIGH;
+            *u = ldexp((double)((1ull << 54) - 2 * m53 - 1), -54);
+        }
+    } else {
+        if (m24 < (1u << 23)) {
+            *side = SIDE_LOW;
+            *u = ldexp((double)(2 * m24 + 1), -25);
+        } else {
+            *side = SIDE_HIGH;
+            *u = ldexp((double)((1u << 25) - 2 * m24 - 1), -25);
+        }
+    }
+    return tail;
+}
+
+/* cos(theta) = 2 U2 - 1 and U2 (1 - U2), both from the integer word. */
+static void polar_uniform(int mode, uint32_t r1, double *cos_t, double *u2_1mu2)
+{
+    if (mode == MODE_FP64) {
+        double lo = (double)r1 + 0.5;             /* U2 * 2^32 */
+        double hi = 4294967296.0 - (double)r1 - 0.5; /* (1 - U2) * 2^32 */
+        *cos_t = ldexp((double)(2 * (int64_t)r1 + 1 - 4294967296LL), -32);
+        *u2_1mu2 = ldexp(lo * hi, -64);
+    } else {
+        uint32_t m = r1 >> 8;
+        double lo = (double)m + 0.5, hi = 16777216.0 - (double)m - 0.5;
+        *cos_t = ldexp((double)(2 * (int64_t)m + 1 - 16777216LL), -24);
+        *u2_1mu2 = ldexp(lo * hi, -48);
+    }
+}
+
+static double azimuth_uniform(int mode, uint32_t r2)
+{
+    if (mode == MODE_FP64)
+        return ldexp((double)r2 + 0.5, -32);
+    return ldexp((double)(r2 >> 8) + 0.5, -24);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inversion of G (Sec. 4).  Solving G(x) = U1 (eq:GU) with the q-logarithm
+ * (eq:qlog) gives
+ *   L = ln_{q*}(1 - U1^(2/3)) = -kappa* {(1 - U1^(2/3))^(-1/kappa*) - 1}  (eq:L)
+ *   x = (V/theta)^2 = root of b x^2 + (a + cL) x + L = 0                   (eq:v)
+ * Written with lT = ln(1 - U1^(2/3)) so that no step subtracts nearly equal
+ * numbers:
+ *   low side : lT = log1p(-exp((2/3) ln U1))
+ *   high side: lT = ln(-expm1((2/3) log1p(-W1)))
+ *   L = -kappa* expm1(-lT / kappa*)
+ * and the two printed forms of the root (eq:v) chosen by the sign of
+ * A = a + cL:  x = -2L / (A + D) if A >= 0, else (D - A) / (2b), with
+ * D = sqrt(A^2 - 4bL).                                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double lT, z, L, A, D, x;
+} inversion;
+
+static void invert(const double *p, int side, double u, inversion *r)
+{
+    double ks = p[OP_KSTAR], a = p[OP_A], b = p[OP_B], c = p[OP_C];
+    double lT;
+    if (side == SIDE_LOW) {
+        double t = exp((2.0 / 3.0) * log(u)); /* U1^(2/3) */
+        lT = log1p(-t);
+    } else {
+        double lnU1 = log1p(-u);               /* ln(1 - W1) = ln U1 */
+        lT = log(-expm1((2.0 / 3.0) * lnU1));  /* ln(1 - U1^(2/3)) */
+    }
+    double z = -lT / ks;
+    double L = -ks * expm1(z);
+    double A = a + c * L;
+    double D = sqrt(A * A - 4.0 * b * L);
+    double x = (A >= 0.0) ? (-2.0 * L) / (A + D) : (D - A) / (2.0 * b);
+    r->lT = lT; r->z = z; r->L = L; r->A = A; r->D = D; r->x = x;
+}
+
+/* Speed V / theta at a given (side, small uniform). */
+double oracle_speed(double kappa, int side, double u)
+{
+    double p[OP_COUNT];
+    inversion r;
+    oracle_params(kappa, p);
+    invert(p, side, u, &r);
+    return sqrt(r.x);
+}
+
+/* The approximate CDF G(x) of eq:G with exp_q from eq:qexp and q* = 1 + 1/kappa*:
+ * exp_{q*}(-w) = (1 + w/kappa*)^(-kappa*), w = (a x + b x^2) / (1 + c x).
+ * Returns G and 1 - G, each computed without cancellation. */
+void oracle_G(double kappa, double x, double *G, double *one_minus_G)
+{
+    double p[OP_COUNT];
+    oracle_params(kappa, p);
+    double ks = p[OP_KSTAR], a = p[OP_A], b = p[OP_B], c = p[OP_C];
+    double w = (a * x + b * x * x) / (1.0 + c * x);
+    double ln_e = -ks * log1p(w / ks);       /* ln exp_{q*}(-w) */
+    double inner = -expm1(ln_e);             /* 1 - exp_{q*}(-w) */
+    *G = exp(1.5 * log(inner));
+    *one_minus_G = -expm1(1.5 * log1p(-exp(ln_e)));
+}
+
+/* The approximate speed density g(x) of eq:approx_x. */
+double oracle_g_pdf(double kappa, double x)
+{
+    double p[OP_COUNT];
+    oracle_params(kappa, p);
+    double ks = p[OP_KSTAR], a = p[OP_A], b = p[OP_B], c = p[OP_C];
+    double ratio = 1.0 + (a * x + b * x * x) / (ks * (1.0 + c * x));
+    double pre = 3.0 * (a + 2.0 * b * x + b * c * x * x) / (2.0 * (1.0 + c * x) * (1.0 + c * x));
+    return pre * sqrt(1.0 - pow(ratio, -ks)) * pow(ratio, -(ks + 1.0));
+}
+
+/* ------------------------------------------------------------------------ */
+/* One particle of Table 1: speed from U1, direction from U2 and U3:
+ *   v_x = V (2U2 - 1), v_y = 2V sqrt(U2(1-U2)) cos(2 pi U3),
+ *   v_z = 2V sqrt(U2(1-U2)) sin(2 pi U3), then the drift is added.        */
+/* ------------------------------------------------------------------------ */
+
+static int one_particle(const double *p, double theta, const double *drift, int mode,
+                        const uint32_t r[4], double v[3])
+{
+    int side;
+    double u;
+    inversion inv;
+    int tail = oracle_speed_uniform(mode, r[0], r[3], &side, &u);
+    invert(p, side, u, &inv);
+    double V = theta * sqrt(inv.x);
+    double cos_t, u2prod;
+    polar_uniform(mode, r[1], &cos_t, &u2prod);
+    double sin_t = 2.0 * sqrt(u2prod);
+    double phi = 2.0 * M_PI * azimuth_uniform(mode, r[2]);
+    v[0] = V * cos_t + drift[0];
+    v[1] = V * sin_t * cos(phi) + drift[1];
+    v[2] = V * sin_t * sin(phi) + drift[2];
+    return tail;
+}
+
+/* Samples particles counter_offset .. counter_offset + n - 1 of segment seg.
+ * Returns the number of particles that took the FP64 tail (mode 1). */
+uint64_t oracle_sample(double kappa, double theta, const double *drift, uint64_t n, uint64_t seed,
+                       uint64_t counter_offset, uint32_t seg, int mode, double *vx, double *vy,
+                       double *vz)
+{
+    double p[OP_COUNT];
+    double zero[3] = {0.0, 0.0, 0.0};
+    const double *d = drift ? drift : zero;
+    uint64_t tails = 0;
+    oracle_params(kappa, p);
+#pragma omp parallel for schedule(static) reduction(+ : tails)
+    for (int64_t j = 0; j < (int64_t)n; ++j) {
+        uint32_t r[4];
+        double v[3];
+        particle_block(seed, counter_offset + (uint64_t)j, seg, 0, r);
+        tails += (uint64_t)one_particle(p, theta, d, mode, r, v);
+        vx[j] = v[0]; vy[j] = v[1]; vz[j] = v[2];
+    }
+    return tails;
+}
+
+/* Same as oracle_sample, for an arbitrary list of particle indices. */
+void oracle_sample_indices(double kappa, double theta, const double *drift, const uint64_t *idx,
+                           uint64_t m, uint64_t seed, uint32_t seg, int mode, double *vx,
+                           double *vy, double *vz)
+{
+    double p[OP_COUNT];
+    double zero[3] = {0.0, 0.0, 0.0};
+    const double *d = drift ? drift : zero;
+    oracle_params(kappa, p);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < (int64_t)m; ++j) {
+        uint32_t r[4];
+        double v[3];
+        particle_block(seed, idx[j], seg, 0, r);
+        one_particle(p, theta, d, mode, r, v);
+        vx[j] = v[0]; vy[j] = v[1]; vz[j] = v[2];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the sampler at fixed uniforms (reparameterisation gradient).
+ * Not in the paper; derived from its equations:
+ *   dv/dtheta = v / theta  (v is linear in theta, Table 1)
+ *   x solves P(x) = b x^2 + (a + cL) x + L = 0 (eq:v), and dP/dx = 2bx + A = D,
+ *   so dx/dkappa = -(b' x^2 + (a' + c' L + c L') x + L') / D,
+ *   with L = -kappa* expm1(z), z = -lT/kappa*, lT independent of kappa:
+ *   L' = -expm1(z) + z e^z;  dv/dkappa = v (dx/dkappa) / (2x).
+ * Returns sum_i g_i . dv_i/dkappa and sum_i g_i . dv_i/dtheta (drift-free). */
+/* ------------------------------------------------------------------------ */
+void oracle_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                     uint32_t seg, int mode, const float *gx, const float *gy, const float *gz,
+                     double out[2])
+{
+    double p[OP_COUNT];
+    oracle_params(kappa, p);
+    double c = p[OP_C], da = p[OP_DA], db = p[OP_DB], dc = p[OP_DC];
+    double sum_k = 0.0, sum_t = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : sum_k, sum_t)
+    for (int64_t j = 0; j < (int64_t)n; ++j) {
+        uint32_t r[4];
+        int side;
+        double u;
+        inversion inv;
+        particle_block(seed, counter_offset + (uint64_t)j, seg, 0, r);
+        oracle_speed_uniform(mode, r[0], r[3], &side, &u);
+        invert(p, side, u, &inv);
+        double V = theta * sqrt(inv.x);
+        double cos_t, u2prod;
+        polar_uniform(mode, r[1], &cos_t, &u2prod);
+        double sin_t = 2.0 * sqrt(u2prod);
+        double phi = 2.0 * M_PI * azimuth_uniform(mode, r[2]);
+        double v0 = V * cos_t, v1 = V * sin_t * cos(phi), v2 = V * sin_t * sin(phi);
+        double s = (double)gx[j] * v0 + (double)gy[j] * v1 + (double)gz[j] * v2;
+        double dL = -expm1(inv.z) + inv.z * exp(inv.z);
+        double x = inv.x, L = inv.L;
+        double dx = -(db * x * x + (da + dc * L + c * dL) * x + dL) / inv.D;
+        sum_k += s * dx / (2.0 * x);
+        sum_t += s / theta;
+    }
+    out[0] = sum_k;
+    out[1] = sum_t;
+}
+
+/* Number of worker threads the oracle's parallel loops use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

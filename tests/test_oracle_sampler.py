@@ -1,0 +1,272 @@
+"""Oracle pins for the per-particle generator (Sec. 4, Table 1) and its adjoint.
+
+Pins (none retypes the inversion):
+  * round trip: the approximate CDF G of eq:G, coded separately in the oracle,
+    evaluated at each sampled speed returns the uniform (eq:GU) to 1e-12,
+    relative to U1 on the low side and to 1 - U1 on the high side;
+  * the uniform maps: exact midpoint dyadics, tail probability exactly 2^-20,
+    the tail refinement stays inside its 24-bit cell;
+  * |v| = V and isotropy of the direction (Table 1, last three rows);
+  * KS of the speeds against the exact Kappa CDF (eq:CDF) at sizes where the
+    approximation error is below the sampling noise, and against G itself;
+  * the paper's statements on the energy error and on the relative entropy
+    (Sec. 3, fig:DE), by quadrature of the oracle's inversion and of its
+    approximate density (eq:approx_x);
+  * the adjoint against central finite differences of the oracle's samples.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_statements.json")))
+
+
+def exact_cdf(x, k):
+    return special.betainc(1.5, k - 0.5, x / (x + k))
+
+
+# ----------------------------------------------------------------------------- round trip
+
+LOW_U = [2.0 ** -54, 2.0 ** -40, 2.0 ** -25, 1e-6, 1e-3, 0.01, 0.1, 0.3, 0.5]
+HIGH_W = [0.5, 0.2, 0.05, 1e-3, 2.0 ** -20, 1e-9, 2.0 ** -40, 2.0 ** -54]
+
+
+@pytest.mark.parametrize("k", [1.6, 2.0, 3.0, 4.1, 7.5, 10.0, 15.0])
+def test_round_trip(orc, k):
+    for u in LOW_U:
+        x = orc.speed(k, orc.SIDE_LOW, u) ** 2
+        g, _ = orc.G(k, x)
+        assert abs(g - u) <= 1e-12 * u, (k, u, g)
+    for w in HIGH_W:
+        x = orc.speed(k, orc.SIDE_HIGH, w) ** 2
+        _, h = orc.G(k, x)
+        assert abs(h - w) <= 1e-12 * w, (k, w, h)
+
+
+def test_speed_monotone_and_continuous_across_sides(orc):
+    k = 3.0
+    lo = orc.speed(k, orc.SIDE_LOW, 0.5)
+    hi = orc.speed(k, orc.SIDE_HIGH, 0.5)
+    assert abs(lo - hi) < 1e-15 * lo
+    us = np.linspace(1e-6, 0.5, 200)
+    v = [orc.speed(k, orc.SIDE_LOW, u) for u in us] + [orc.speed(k, orc.SIDE_HIGH, w) for w in us[::-1][1:]]
+    assert np.all(np.diff(v) > 0)
+
+
+def test_paper_root_forms_agree_where_well_conditioned(orc):
+    """Table 1 as printed (rationalised root of eq:v, eq:L) equals the oracle's
+    stable form where the printed form has no cancellation."""
+    for k in (1.6, 3.0, 10.0):
+        p = orc.params(k)
+        a, b, c, ks = p["a"], p["b"], p["c"], p["kstar"]
+        for u in (0.02, 0.1, 0.5, 0.9, 0.99):
+            L = -ks * ((1 - u ** (2 / 3)) ** (-1 / ks) - 1)
+            v_paper = math.sqrt(-2 * L / ((a + c * L) + math.sqrt((a + c * L) ** 2 - 4 * b * L)))
+            side, small = (orc.SIDE_LOW, u) if u <= 0.5 else (orc.SIDE_HIGH, 1 - u)
+            assert abs(orc.speed(k, side, small) / v_paper - 1) < 1e-12
+
+
+# ----------------------------------------------------------------------------- uniform maps
+
+def test_fp64_speed_uniform_map(orc):
+    rng = np.random.default_rng(0)
+    words = rng.integers(0, 1 << 32, size=(2000, 2), dtype=np.uint64)
+    words = np.vstack([words, [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0x80000000, 0], [0x7FFFFFFF, 0xFFFFFFFF]]])
+    for r0, r3 in words:
+        tail, side, u = orc.speed_uniform(orc.MODE_FP64, int(r0), int(r3))
+        m = ((int(r0) << 32) | int(r3)) >> 11
+        assert not tail
+        # U1 is the midpoint of cell m of 2^53 equal cells, and exact
+        if m < (1 << 52):
+            assert side == orc.SIDE_LOW and u == (2 * m + 1) * 2.0 ** -54
+        else:
+            assert side == orc.SIDE_HIGH and u == ((1 << 54) - 2 * m - 1) * 2.0 ** -54
+        assert 0 < u <= 0.5
+
+
+def test_fp32_speed_uniform_map_and_tail(orc):
+    edge = [0, 1, (1 << 23) - 1, 1 << 23, (1 << 24) - 17, (1 << 24) - 16, (1 << 24) - 1]
+    rng = np.random.default_rng(1)
+    cells = edge + rng.integers(0, 1 << 24, size=3000).tolist()
+    for m24 in cells:
+        for low8, r3 in ((0, 0), (255, 0xFFFFFFFF), (17, 12345)):
+            r0 = (m24 << 8) | low8
+            tail, side, u = orc.speed_uniform(orc.MODE_FP32, r0, r3)
+            assert tail == (m24 >= (1 << 24) - 16)
+            if not tail:
+                if m24 < (1 << 23):
+                    assert side == orc.SIDE_LOW and u == (2 * m24 + 1) * 2.0 ** -25
+                else:
+                    assert side == orc.SIDE_HIGH and u == ((1 << 25) - 2 * m24 - 1) * 2.0 ** -25
+            else:
+                # the 53-bit refinement lies inside the same 24-bit cell, whose W1 range
+                # is (2^24 - m24 - 1, 2^24 - m24] * 2^-24
+                assert side == orc.SIDE_HIGH
+                assert ((1 << 24) - m24 - 1) * 2.0 ** -24 < u <= ((1 << 24) - m24) * 2.0 ** -24
+                assert u < 2.0 ** -20
+                t2, s2, u2 = orc.speed_uniform(orc.MODE_FP32_NOTAIL, r0, r3)
+                assert not t2 and s2 == orc.SIDE_HIGH and u2 == ((1 << 25) - 2 * m24 - 1) * 2.0 ** -25
+
+
+def test_tail_probability_is_two_to_minus_20(orc):
+    """16 of the 2^24 cells take the tail: count them exactly."""
+    tails = sum(orc.speed_uniform(orc.MODE_FP32, (m << 8), 0)[0] for m in range((1 << 24) - 64, 1 << 24))
+    assert tails == 16 and 16 / 2 ** 24 == 2.0 ** -20
+    # the oracle's sampler counts about N 2^-20 tail particles
+    n = 1 << 22
+    *_, t = orc.sample(1.6, 1.0, n, 5, mode=orc.MODE_FP32)
+    assert abs(t - n * 2.0 ** -20) < 5 * math.sqrt(n * 2.0 ** -20)
+
+
+# ----------------------------------------------------------------------------- direction
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_norm_equals_speed_and_isotropy(orc, mode):
+    n = 200_000
+    vx, vy, vz, _ = orc.sample(3.0, 1.7, n, 21, mode=mode)
+    blocks = orc.philox_blocks(n, 21)
+    sp = np.array([1.7 * orc.speed(3.0, *orc.speed_uniform(mode, int(b[0]), int(b[3]))[1:]) for b in blocks[:2000]])
+    norm = np.sqrt(vx ** 2 + vy ** 2 + vz ** 2)
+    np.testing.assert_allclose(norm[:2000], sp, rtol=1e-14)
+    cos_t = vx / norm
+    phi = np.arctan2(vz, vy)
+    assert stats.kstest(cos_t, stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+    assert stats.kstest(phi, stats.uniform(loc=-math.pi, scale=2 * math.pi).cdf).pvalue > 1e-3
+    for comp in (vx, vy, vz):
+        # mean zero: speeds have finite variance at kappa = 3
+        assert abs(comp.mean()) < 6 * comp.std() / math.sqrt(n)
+
+
+# ----------------------------------------------------------------------------- distribution
+
+@pytest.mark.parametrize("k", [1.6, 2.0, 3.0, 4.0, 6.0, 10.0])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ks_against_exact_kappa(orc, k, mode):
+    """At N = 2e5 the approximation's sup|G - F| (largest 1.2e-3 at kappa 4) is
+    below the KS noise, so the samples pass against the exact CDF."""
+    n = 200_000
+    vx, vy, vz, _ = orc.sample(k, 1.0, n, 1000 + int(10 * k), mode=mode)
+    x = vx ** 2 + vy ** 2 + vz ** 2
+    assert stats.kstest(x, lambda t: exact_cdf(t, k)).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("k", [1.6, 4.1, 10.0])
+def test_ks_against_G(orc, k):
+    """Against its own target G the sampler passes at any size."""
+    n = 1_000_000
+    vx, vy, vz, _ = orc.sample(k, 1.0, n, 77)
+    x = vx ** 2 + vy ** 2 + vz ** 2
+    cdf = np.array([orc.G(k, t)[0] for t in np.sort(x)[:: n // 20000]])
+    emp = (np.arange(0, n, n // 20000) + 0.5) / n
+    assert np.max(np.abs(cdf - emp)) < 1.95 / math.sqrt(n) + 1e-5
+
+
+def _mean_x(orc, k):
+    f_lo = lambda u: orc.speed(k, orc.SIDE_LOW, u) ** 2
+    f_hi = lambda w: orc.speed(k, orc.SIDE_HIGH, w) ** 2
+    a, _ = integrate.quad(f_lo, 0, 0.5, limit=200, epsabs=0, epsrel=1e-12)
+    b, _ = integrate.quad(f_hi, 0, 0.5, limit=400, epsabs=0, epsrel=1e-12)
+    return a + b
+
+
+def test_energy_error_matches_paper(orc):
+    """<x> = int_0^1 x(U) dU against the exact 3k/(2k-3) of eq:kappaE."""
+    bound = GOLD["energy_error_bound"]["value"]
+    err = {k: _mean_x(orc, k) / (3 * k / (2 * k - 3)) - 1 for k in (2.0, 2.3, 2.7, 3.0, 4.1, 6.0, 7.5, 10.0)}
+    for k, e in err.items():
+        if k != 4.1:
+            assert abs(e) < bound, (k, e)
+    assert abs(math.log10(abs(err[4.1])) - GOLD["energy_error_at_transition"]["log10_approx"]) < 0.5
+    # the error changes sign near kappa 2.5
+    assert err[2.3] * err[2.7] < 0
+    kz = GOLD["energy_error_zero_kappa"]["approx"]
+    from scipy.optimize import brentq
+    root = brentq(lambda k: _mean_x(orc, k) / (3 * k / (2 * k - 3)) - 1, 2.3, 2.7, xtol=1e-3)
+    assert abs(root - kz) < 0.1
+
+
+def _relative_entropy(orc, k):
+    lnB = special.betaln(1.5, k - 0.5)
+
+    def f(x):
+        return math.exp(-math.log(k) - lnB + 0.5 * math.log(x / k) - (k + 1) * math.log1p(x / k))
+
+    def integrand(x):
+        if x <= 0:
+            return 0.0
+        fx = f(x)
+        return fx * math.log(fx / orc.g_pdf(k, x)) if fx > 0 else 0.0
+
+    edges = [0, 1e-6, 1e-3, 0.1, 1, 3, 10, 30, 100, 1e3, 1e4, 1e5, 1e6, 1e8, 1e10, np.inf]
+    return sum(integrate.quad(integrand, lo, hi, limit=400, epsabs=1e-16, epsrel=1e-10)[0]
+               for lo, hi in zip(edges[:-1], edges[1:]))
+
+
+def test_relative_entropy_matches_paper(orc):
+    """eq:relative_entropy between eq:kappax and the oracle's g (eq:approx_x)."""
+    dip_grid = np.arange(2.3, 2.95, 0.05)
+    d = [_relative_entropy(orc, k) for k in dip_grid]
+    assert abs(dip_grid[int(np.argmin(d))] - GOLD["relative_entropy_dip_kappa"]["approx"]) < 0.11
+    assert min(d) > 0
+    peak_grid = np.arange(3.8, 4.65, 0.1)
+    d = [_relative_entropy(orc, k) for k in peak_grid]
+    assert abs(peak_grid[int(np.argmax(d))] - GOLD["relative_entropy_peak_kappa"]["approx"]) < 0.11
+    level = GOLD["relative_entropy_high_kappa_level"]["approx"]
+    hi = [_relative_entropy(orc, k) for k in (5.0, 6.0, 7.5, 10.0)]
+    assert all(level / 3 < v < level * 3 for v in hi)
+    assert all(_relative_entropy(orc, k) < 1e-6 for k in (2.0, 2.5, 3.0))  # remarkably low below 4
+
+
+def test_g_pdf_is_the_derivative_of_G(orc):
+    for k in (1.6, 3.0, 10.0):
+        for x in (0.01, 0.5, 1.0, 4.0, 50.0):
+            h = 1e-6 * x
+            # difference whichever of G and 1 - G is small, to avoid cancellation
+            if orc.G(k, x)[0] < 0.5:
+                fd = (orc.G(k, x + h)[0] - orc.G(k, x - h)[0]) / (2 * h)
+            else:
+                fd = (orc.G(k, x - h)[1] - orc.G(k, x + h)[1]) / (2 * h)
+            assert abs(orc.g_pdf(k, x) / fd - 1) < 1e-6
+
+
+# ----------------------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("k,theta", [(2.5, 1.3), (1.6, 1.0), (7.5, 0.7)])
+def test_adjoint_against_central_differences(orc, mode, k, theta):
+    n = 100_000
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((3, n)).astype(np.float32)
+    dk, dt = orc.backward(k, theta, n, 9, g[0], g[1], g[2], mode=mode)
+    h = 1e-4
+
+    def loss(kk, tt):
+        vx, vy, vz, _ = orc.sample(kk, tt, n, 9, mode=mode)
+        return float(np.dot(g[0].astype(np.float64), vx) + np.dot(g[1].astype(np.float64), vy)
+                     + np.dot(g[2].astype(np.float64), vz))
+
+    fd_k = (loss(k + h, theta) - loss(k - h, theta)) / (2 * h)
+    fd_t = (loss(k, theta + h) - loss(k, theta - h)) / (2 * h)
+    assert abs(dk - fd_k) < 1e-6 * abs(fd_k), (dk, fd_k)
+    assert abs(dt - fd_t) < 1e-9 * abs(fd_t), (dt, fd_t)
+
+
+def test_adjoint_single_particles_at_extreme_uniforms(orc):
+    """Per-particle dv/dkappa where U1 is tiny or 1 - U1 is tiny."""
+    n = 1 << 20
+    blocks = orc.philox_blocks(n, 31)
+    m53 = ((blocks[:, 0].astype(np.uint64) << np.uint64(32)) | blocks[:, 3].astype(np.uint64)) >> np.uint64(11)
+    picks = [int(np.argmin(m53)), int(np.argmax(m53)), int(np.argsort(m53)[n // 2])]
+    k, h = 3.0, 1e-5
+    one = np.ones(1, dtype=np.float32)
+    zero = np.zeros(1, dtype=np.float32)
+    for j in picks:
+        dk, _ = orc.backward(k, 1.0, 1, 31, one, zero, zero, counter_offset=j)
+        up = orc.sample(k + h, 1.0, 1, 31, counter_offset=j)[0][0]
+        dn = orc.sample(k - h, 1.0, 1, 31, counter_offset=j)[0][0]
+        fd = (up - dn) / (2 * h)
+        assert abs(dk - fd) < 1e-7 * abs(fd) + 1e-300, (j, dk, fd)
