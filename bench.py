@@ -1,0 +1,232 @@
+"""Benchmark of the approximate Kappa velocity generator on one MI355X.
+
+One step = one pass of the generator over the C2 workload: 1e8 particles for
+each kappa in {1.6, 2, 3, 4, 6, 10}, theta 1, FP32 with the FP64 tail
+inversion, seed 1 (the paper's third test generates 1e8 particles over a
+range of kappa, Sec. 5).  Outputs stay resident in HBM; nothing is copied to
+the host inside the timed region.
+
+Prints one JSON line: the headline throughput (particles/s), the roofline of
+the dominant kernel (HBM write bytes per launch over its event-timed duration,
+against the 8 TB/s peak), the same GPU's exact generators and FP64 path, the
+backward and batched forms, and the CPU oracle as a baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "particles/sec (3D velocities) and % HBM-write roofline vs same-GPU exact generator"
+KERNEL_SOURCES = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/forward.hip",
+                  "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_fp32_c2.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when they are missing or were taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return {"write_bytes": t["write_bytes_per_launch"], "fetch_bytes": t["fetch_bytes_per_launch"],
+            "algorithmic_bytes": launch_bytes, "calibration": t.get("calibration")}
+
+
+def time_launches(fn, reps, torch):
+    """Average duration (ms) of fn() over reps launches, HIP events on the
+    current stream (the one the library launches on)."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for s, e in zip(starts, ends):
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / reps
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle (FP64 arithmetic at the FP32 mode's uniforms, OpenMP over
+    particles) timed on the host over a bounded sample of the C2 workload."""
+    import numpy as np  # noqa: F401
+    sys.path.insert(0, ROOT)
+    import oracle
+    import workloads
+    c = workloads.C2
+    probe_n = 200_000
+    t0 = time.perf_counter()
+    oracle.sample(c["kappas"][0], c["theta"], probe_n, c["seed"], mode=oracle.MODE_FP32)
+    rate = probe_n / max(time.perf_counter() - t0, 1e-6)
+    per_kappa = int(min(c["n"], max(1e5, rate * seconds_target / len(c["kappas"]))))
+    t0 = time.perf_counter()
+    for k in c["kappas"]:
+        oracle.sample(k, c["theta"], per_kappa, c["seed"], mode=oracle.MODE_FP32)
+    dt = time.perf_counter() - t0
+    return {"value": per_kappa * len(c["kappas"]) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {per_kappa} particles of each of the 6 C2 kappa values (FP32-mode uniforms, "
+                      f"FP64 arithmetic), {dt:.1f} s on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the generator needs no communication, and a run on N GPUs is "
+              "N independent counter ranges (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    import paper_2602_05606_amd as kp
+    import workloads
+
+    c = workloads.C2
+    n, kappas, theta, seed = c["n"], c["kappas"], c["theta"], c["seed"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"{torch.cuda.get_device_name(dev)}; library {kp.version()}")
+    out32 = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+
+    def step(out=out32, prec=kp.FP32, events=None):
+        for k in kappas:
+            if events is not None:
+                events[0].append(torch.cuda.Event(enable_timing=True))
+                events[1].append(torch.cuda.Event(enable_timing=True))
+                events[0][-1].record()
+            kp.sample(k, theta, n, seed, precision=prec, out=out)
+            if events is not None:
+                events[1][-1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done; timing {args.steps} steps")
+    events = ([], [])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(events=events)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(*events)]
+    avg_kernel_ms = sum(kernel_ms) / len(kernel_ms)
+    particles = args.steps * len(kappas) * n
+    value = particles / elapsed
+    launch_bytes = 12 * n
+    achieved = launch_bytes / (avg_kernel_ms * 1e-3) / 1e9
+    log(f"timed: {elapsed * 1e3 / args.steps:.3f} ms/step, {value:.4e} particles/s, kernel {avg_kernel_ms:.4f} ms "
+        f"= {achieved:.1f} GB/s")
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C2 single-species sweep: 1e8 particles per kappa in {1.6,2,3,4,6,10}, theta 1, "
+                               "FP32 bulk + FP64 tail (1-U1 < 2^-20), Philox4x32-10 seed 1, SoA outputs resident in HBM",
+                   "particles_per_step": len(kappas) * n, "kappas": list(kappas), "precision": "FP32+FP64tail"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
+                     "kernel": "forward_kernel<FP32 tail, 4 particles/thread>",
+                     "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
+    }
+
+    if not args.no_extras:
+        extras = {}
+        per_kappa = {}
+        for k in kappas:
+            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
+            per_kappa[str(k)] = n / (ms * 1e-3)
+        extras["fp32_per_kappa_particles_per_s"] = per_kappa
+        fill_ms = time_launches(lambda: kp.fill_probe(n, kp.FP32, out32), 5, torch)
+        extras["store_probe_fp32"] = {"GB_per_s": 12 * n / (fill_ms * 1e-3) / 1e9,
+                                      "particles_per_s": n / (fill_ms * 1e-3)}
+        result["roofline"]["frac_of_store_probe"] = achieved / extras["store_probe_fp32"]["GB_per_s"]
+        log("store probe done")
+        exact = {}
+        for k in kappas:
+            t_ms = time_launches(lambda: kp.sample_exact_t(k, theta, n, seed, precision=kp.FP32, out=out32), 3, torch)
+            p_ms = time_launches(lambda: kp.sample_exact_pareto(k, theta, n, seed, precision=kp.FP32, out=out32), 3,
+                                 torch)
+            rate_t, rate_p = n / (t_ms * 1e-3), n / (p_ms * 1e-3)
+            exact[str(k)] = {"t_gamma": rate_t, "pareto": rate_p,
+                             "approx_speedup_vs_t": per_kappa[str(k)] / rate_t,
+                             "approx_speedup_vs_pareto": per_kappa[str(k)] / rate_p}
+        extras["exact_generators_fp32_particles_per_s"] = exact
+        log("exact generators done")
+        del out32
+        out64 = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+        fp64 = {}
+        for k in kappas:
+            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP64, out=out64), 3, torch)
+            fp64[str(k)] = {"particles_per_s": n / (ms * 1e-3), "GB_per_s": 24 * n / (ms * 1e-3) / 1e9}
+        extras["fp64_per_kappa"] = fp64
+        fill64 = time_launches(lambda: kp.fill_probe(n, kp.FP64, out64), 3, torch)
+        extras["store_probe_fp64_GB_per_s"] = 24 * n / (fill64 * 1e-3) / 1e9
+        del out64
+        log("FP64 sweep done")
+        c3 = workloads.C3
+        gen = torch.Generator(device=dev).manual_seed(c3["grad_seed"])
+        g = torch.randn((3, c3["n"]), generator=gen, device=dev, dtype=torch.float32)
+        ws = torch.empty(kp.backward_workspace_bytes(c3["n"]), dtype=torch.uint8, device=dev)
+        bw_ms = time_launches(lambda: kp.sample_backward(c3["kappa"], c3["theta"], c3["n"], c3["seed"], g[0], g[1],
+                                                         g[2], precision=kp.FP32, workspace=ws), 5, torch)
+        extras["backward_c3"] = {"particles_per_s": c3["n"] / (bw_ms * 1e-3), "ms": bw_ms,
+                                 "GB_per_s_read": 12 * c3["n"] / (bw_ms * 1e-3) / 1e9}
+        del g
+        log("backward done")
+        segs = workloads.batched_segments()
+        with kp.Plan(segs, workloads.C4["seed"], kp.FP32) as plan:
+            outb = plan.outputs()
+            default_shape = plan.shape
+            plan.launch(outb)
+            tuned = plan.autotune(outb, reps=5)
+            direct_ms = time_launches(lambda: plan.launch(outb), 20, torch)
+            plan.graph_launch(outb)
+            graph_ms = time_launches(lambda: plan.graph_launch(outb), 20, torch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(50):
+                plan.graph_launch(outb)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3 / 50
+            extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
+                                    "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
+                                    "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3)}
+        log("batched done")
+        result["extras"] = extras
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline done")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

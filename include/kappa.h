@@ -1,0 +1,243 @@
+/*
+ * kappa.h -- C ABI of libkappa, an MI355X (gfx950) implementation of the
+ * approximate Kappa velocity generator of Zenitani & Umeda, "An approximate
+ * Kappa generator for particle simulations" (arXiv 2602.05606).
+ *
+ * The generator (Table 1 of the paper) draws three uniforms per particle,
+ * inverts the q-exponential approximation G of the Kappa speed CDF in closed
+ * form (Sec. 3, eq:G; Sec. 4, eq:GU, eq:qlog, eq:v, eq:L), scatters the speed
+ * isotropically and scales it by theta, the most probable speed of the Kappa
+ * distribution (Sec. 2, eq:kappa).  It has no loops or rejection steps.
+ *
+ * Conventions shared by every entry point:
+ *
+ *   kappa    Kappa index; the distribution needs kappa > 3/2 (Sec. 2).  The
+ *            fitted parameter c of eq:c covers kappa in [1.5, 10] (Sec. 3);
+ *            larger values are accepted.  kappa <= 3/2, NaN or Inf: KAPPA_EINVAL.
+ *   theta    most probable speed, > 0 and finite, else KAPPA_EINVAL.
+ *   seed     64-bit Philox4x32-10 key: key = (low 32 bits, high 32 bits).
+ *   counters particle i of segment seg draws the Philox4x32-10 block with
+ *            counter (low 32 bits of i, high 32 bits of i, seg, draw), draw = 0
+ *            for the generator.  i = counter_offset + position in the output.
+ *            Output therefore depends only on (kappa, theta, drift, seed, i,
+ *            seg, precision): never on grid, block, unroll, stream or device,
+ *            and a range can be produced in chunks by advancing counter_offset.
+ *   uniforms U1 from the Philox words (r0, r3), U2 from r1, U3 from r2, as
+ *            open midpoint dyadics (see KAPPA_FP64 / KAPPA_FP32 below).
+ *   outputs  structure-of-arrays vx[n], vy[n], vz[n], device pointers owned by
+ *            the caller, written and never read.  double for KAPPA_FP64,
+ *            float for KAPPA_FP32 and KAPPA_FP32_NOTAIL.  Each pointer must be
+ *            aligned to its element size (else KAPPA_EALIGN); 16-byte aligned
+ *            pointers take the vector-store path.
+ *   stream   a hipStream_t passed as void*; NULL is the legacy default stream.
+ *            Calls are asynchronous on the stream unless stated otherwise.
+ *   errors   return codes only; nothing aborts or throws across the ABI.
+ *            Arguments are validated before any HIP call.  A HIP failure
+ *            returns KAPPA_EDEVICE and kappa_last_error() gives the message.
+ *   device   the current HIP device must be gfx950, else KAPPA_EUNSUPPORTED.
+ */
+#ifndef KAPPA_H
+#define KAPPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(KAPPA_BUILDING_LIBRARY)
+#define KAPPA_API __attribute__((visibility("default")))
+#else
+#define KAPPA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KAPPA_OK = 0,
+    KAPPA_EINVAL = 1,      /* invalid argument */
+    KAPPA_EALIGN = 2,      /* pointer not aligned to its element size */
+    KAPPA_EDEVICE = 3,     /* HIP runtime error */
+    KAPPA_ENOMEM = 4,      /* device allocation failed (plans only) */
+    KAPPA_EUNSUPPORTED = 5,/* current device is not gfx950 */
+    KAPPA_ERANGE = 6       /* size outside a documented limit */
+} kappa_status;
+
+typedef enum {
+    /* All FP64.  U1 has 53 bits: m = top 53 bits of (r0:r3); U1 = (2m+1) 2^-54
+     * if m < 2^52, else 1 - U1 = (2^54 - 2m - 1) 2^-54; U2 = (r1 + 1/2) 2^-32,
+     * U3 = (r2 + 1/2) 2^-32.  double outputs. */
+    KAPPA_FP64 = 0,
+    /* FP32 bulk with an FP64 tail.  U1 from m24 = r0 >> 8 by the same map with
+     * 24 bits, U2, U3 from the top 24 bits of r1, r2.  When 1 - U1 < 2^-20
+     * (m24 >= 2^24 - 16, probability 2^-20) the inversion is redone in FP64
+     * with the 53-bit U1 of KAPPA_FP64 and the speed rounded to float.
+     * float outputs. */
+    KAPPA_FP32 = 1,
+    /* KAPPA_FP32 without the FP64 tail (diagnostics only). float outputs. */
+    KAPPA_FP32_NOTAIL = 2
+} kappa_precision;
+
+/* Per-species parameter block of Table 1 (rows 1-4), with the kappa
+ * derivatives the backward pass uses, as returned by kappa_params(). */
+enum {
+    KAPPA_P_KSTAR = 0,  /* kappa* = kappa - 1/2 (eq:k2) */
+    KAPPA_P_A,          /* a (eq:a) */
+    KAPPA_P_B,          /* b = (b/c) c (eq:b) */
+    KAPPA_P_C,          /* c = c_approx (eq:c) */
+    KAPPA_P_B_OVER_C,   /* b/c (eq:b) */
+    KAPPA_P_DA,         /* da/dkappa */
+    KAPPA_P_DB,         /* db/dkappa */
+    KAPPA_P_DC,         /* dc/dkappa */
+    KAPPA_P_LNBETA,     /* ln B(3/2, kappa*) */
+    KAPPA_NPARAMS
+};
+
+/* kappa_params -- the setup rows of Table 1 (once per species), in FP64 on
+ * the host: kappa*, a, c, b per eq:k2, eq:a, eq:c, eq:b, with
+ * B(3/2, kappa*) = Gamma(3/2) Gamma(kappa*) / Gamma(kappa + 1) (Sec. 6), and
+ * their kappa-derivatives.  out: host array of KAPPA_NPARAMS doubles, indexed
+ * by KAPPA_P_*.  No HIP call.  KAPPA_EINVAL for a bad kappa or NULL out. */
+KAPPA_API kappa_status kappa_params(double kappa, double *out);
+
+/* kappa_sample -- one species: particles counter_offset .. counter_offset+n-1
+ * of segment seg_id, Table 1 per particle (Sec. 4).  vx, vy, vz: device arrays
+ * of n elements (see conventions).  n = 0 is a no-op returning KAPPA_OK.
+ * counter_offset + n must not exceed 2^64 (KAPPA_EINVAL). */
+KAPPA_API kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed,
+                          uint64_t counter_offset, uint32_t seg_id, int precision,
+                          void *vx, void *vy, void *vz, void *stream);
+
+/* One segment of a batched launch: a species (kappa, theta) in one cell
+ * (drift) with count particles.  Its particles use counters
+ * (0 .. count-1, seg_id, 0), so segment s of a batched call equals
+ * kappa_sample(kappa, theta, count, seed, 0, seg_id, ...) plus drift. */
+typedef struct {
+    double kappa;
+    double theta;
+    double drift[3]; /* added to (vx, vy, vz) after sampling (Galilean shift) */
+    uint64_t count;
+    uint32_t seg_id;
+    uint32_t reserved; /* must be 0 */
+} kappa_segment;
+
+/* Opaque batched plan: device copies of the segment table and of the tile ->
+ * segment map, the chosen launch shape, and a captured hipGraph. */
+typedef struct kappa_plan_s *kappa_plan;
+
+/* Limits of a batched plan. */
+#define KAPPA_MAX_SEGMENTS (1u << 24)
+
+/* kappa_plan_create -- validate segs (host array of nseg, 1 <= nseg <=
+ * KAPPA_MAX_SEGMENTS, each with a valid kappa and theta, finite drift,
+ * reserved = 0), compute each segment's Table 1 setup in FP64 on the host,
+ * lay segments out back to back in the given order (segment s starts at the
+ * sum of the earlier counts), and upload the tables.  Allocates device memory
+ * (KAPPA_ENOMEM on failure) on the current device; synchronous.  *out owns it
+ * until kappa_plan_destroy.  Segments with count 0 are allowed. */
+KAPPA_API kappa_status kappa_plan_create(const kappa_segment *segs, uint32_t nseg, uint64_t seed, int precision,
+                               kappa_plan *out);
+
+/* Total number of particles of the plan (sum of counts). */
+KAPPA_API kappa_status kappa_plan_total(kappa_plan plan, uint64_t *total);
+
+/* kappa_plan_launch -- one persistent-kernel launch writing all segments into
+ * vx, vy, vz (device arrays of kappa_plan_total elements).  Asynchronous. */
+KAPPA_API kappa_status kappa_plan_launch(kappa_plan plan, void *vx, void *vy, void *vz, void *stream);
+
+/* kappa_plan_graph_launch -- same output as kappa_plan_launch, through a
+ * hipGraph holding the one persistent launch.  The graph is captured on the
+ * first call (and again if vx, vy, vz or the launch shape change) and then
+ * replayed with hipGraphLaunch on stream.  Asynchronous. */
+KAPPA_API kappa_status kappa_plan_graph_launch(kappa_plan plan, void *vx, void *vy, void *vz, void *stream);
+
+/* kappa_plan_autotune -- time every launch shape (block size, particles per
+ * thread, workgroups per CU) of the persistent kernel on this plan with HIP
+ * events, keep the fastest, and record it in the autotune cache file (path in
+ * the KAPPA_AUTOTUNE_CACHE environment variable, if set).  Writes vx, vy, vz.
+ * Synchronous.  reps: timed launches per shape (>= 1). */
+KAPPA_API kappa_status kappa_plan_autotune(kappa_plan plan, void *vx, void *vy, void *vz, int reps, void *stream);
+
+/* The launch shape the plan uses: block size, particles per thread, grid. */
+KAPPA_API kappa_status kappa_plan_shape(kappa_plan plan, int *block, int *unroll, int *grid);
+
+/* Set the launch shape explicitly (block in {64,128,256}, unroll in {1,2,4,8},
+ * grid >= 1; KAPPA_EINVAL otherwise).  Output does not depend on the shape. */
+KAPPA_API kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int grid);
+
+/* Release the plan's device memory and graph.  NULL is a no-op. */
+KAPPA_API kappa_status kappa_plan_destroy(kappa_plan plan);
+
+/* kappa_sample_batched -- many species and cells in one persistent launch:
+ * creates a plan, launches it on stream, waits for it and destroys the plan.
+ * Synchronous.  vx, vy, vz hold the sum of the counts. */
+KAPPA_API kappa_status kappa_sample_batched(const kappa_segment *segs, uint32_t nseg, uint64_t seed, int precision,
+                                  void *vx, void *vy, void *vz, void *stream);
+
+/* Workspace the backward pass needs for n particles, in bytes. */
+KAPPA_API size_t kappa_backward_workspace_bytes(uint64_t n);
+
+/* kappa_sample_backward -- reparameterisation gradient of a loss through the
+ * samples of kappa_sample (same kappa, theta, n, seed, counter_offset,
+ * seg_id, precision), at fixed uniforms.  Not in the paper; it differentiates
+ * Table 1: dv/dtheta = v/theta, and dv/dkappa = v (dx/dkappa) / (2x), where
+ * x = (V/theta)^2 solves b x^2 + (a + cL) x + L = 0 (eq:v, eq:L), so
+ * dx/dkappa = -(b' x^2 + (a' + c' L + c L') x + L') / sqrt((a+cL)^2 - 4bL).
+ *   gx, gy, gz  device arrays of n upstream gradients dLoss/dv (double for
+ *               KAPPA_FP64, float otherwise), read only.
+ *   grad        device array of 2 doubles, written: (sum_i g_i . dv_i/dkappa,
+ *               sum_i g_i . dv_i/dtheta), accumulated in FP64 in a fixed order.
+ *   workspace   device scratch of at least kappa_backward_workspace_bytes(n)
+ *               bytes (KAPPA_ERANGE if smaller), 256-byte aligned, owned by
+ *               the caller; its contents are overwritten.
+ * n = 0 writes zeros.  Asynchronous. */
+KAPPA_API kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint64_t seed,
+                                   uint64_t counter_offset, uint32_t seg_id, int precision,
+                                   const void *gx, const void *gy, const void *gz, double *grad,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* kappa_philox -- raw Philox4x32-10 blocks for particles counter_offset ..
+ * counter_offset+n-1 of segment seg_id and draw number draw: out is a device
+ * array of 4n uint32 words (r0, r1, r2, r3 per particle).  For bit-exact
+ * tests of the generator's counter stream. */
+KAPPA_API kappa_status kappa_philox(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id, uint32_t draw,
+                          uint32_t *out, void *stream);
+
+/* Same-GPU exact Kappa generators used as performance comparators (Sec. 5,
+ * third test; Sec. 6).  Both sample the exact distribution of eq:kappa with
+ * rejection loops on the same Philox stream: iteration t of particle i uses
+ * the block with counter (i, 0, t).  precision KAPPA_FP64 (double outputs) or
+ * KAPPA_FP32 (float outputs, FP32 arithmetic).  iters: optional device array
+ * of n uint32 (NULL to skip) receiving the number of rejection-loop
+ * iterations each particle took.
+ *   kappa_sample_exact_t: the multivariate-t form: three normals (Box-Muller)
+ *     times sqrt(kappa / (2 G)), G ~ Gamma(kappa - 1/2) by Marsaglia-Tsang.
+ *   kappa_sample_exact_pareto: speed by acceptance-rejection from a Type II
+ *     Pareto (Lomax) proposal with index n = kappa/2, isotropic direction. */
+KAPPA_API kappa_status kappa_sample_exact_t(double kappa, double theta, uint64_t n, uint64_t seed, int precision,
+                                  void *vx, void *vy, void *vz, uint32_t *iters, void *stream);
+KAPPA_API kappa_status kappa_sample_exact_pareto(double kappa, double theta, uint64_t n, uint64_t seed, int precision,
+                                       void *vx, void *vy, void *vz, uint32_t *iters, void *stream);
+
+/* Measurement probes.
+ * kappa_fill_probe: store-only kernel writing the constant pattern 1, 2, 3 to
+ *   vx, vy, vz (n elements of the precision's type) with the generator's store
+ *   path; its rate is the achievable HBM-write ceiling.
+ * kappa_copy_probe: plain copy of bytes from src to dst (device pointers,
+ *   16-byte aligned, bytes a multiple of 16) to calibrate traffic counters. */
+KAPPA_API kappa_status kappa_fill_probe(uint64_t n, int precision, void *vx, void *vy, void *vz, void *stream);
+KAPPA_API kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t bytes, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+KAPPA_API const char *kappa_status_string(kappa_status status);
+
+/* Message of the last failing call on this thread (static per-thread storage). */
+KAPPA_API const char *kappa_last_error(void);
+
+/* Library version string. */
+KAPPA_API const char *kappa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KAPPA_H */

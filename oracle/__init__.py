@@ -61,6 +61,10 @@ def _load():
     lib.oracle_sample_indices.restype = None
     lib.oracle_backward.argtypes = [c_d, c_d, c_u64, c_u64, c_u64, c_u32, c_int, fp, fp, fp, dp]
     lib.oracle_backward.restype = None
+    lib.oracle_find_tails.argtypes = [c_u64, c_u64, c_u64, c_u32, u64p, c_u64]
+    lib.oracle_find_tails.restype = c_u64
+    lib.oracle_dot.argtypes = [c_d, c_d, c_u64, c_u64, c_u64, c_u32, c_int, fp, fp, fp]
+    lib.oracle_dot.restype = c_d
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = c_int
     lib.oracle_set_num_threads.argtypes = [c_int]
@@ -167,6 +171,23 @@ def backward(kappa, theta, n, seed, gx, gy, gz, counter_offset=0, seg=0, mode=MO
                         _ptr(gx, ctypes.c_float), _ptr(gy, ctypes.c_float), _ptr(gz, ctypes.c_float),
                         _ptr(out, ctypes.c_double))
     return float(out[0]), float(out[1])
+
+
+def find_tails(n, seed, counter_offset=0, seg=0, max_out=4096):
+    """Particle indices whose FP32-mode uniform takes the FP64 tail."""
+    out = np.zeros(max_out, dtype=np.uint64)
+    found = _load().oracle_find_tails(n, seed, counter_offset, seg, _ptr(out, ctypes.c_uint64), max_out)
+    return out[:min(found, max_out)].copy()
+
+
+def dot(kappa, theta, n, seed, gx, gy, gz, counter_offset=0, seg=0, mode=MODE_FP64):
+    """sum_i g_i . v_i over the samples, in FP64."""
+    gx = np.ascontiguousarray(gx, dtype=np.float32)
+    gy = np.ascontiguousarray(gy, dtype=np.float32)
+    gz = np.ascontiguousarray(gz, dtype=np.float32)
+    assert gx.size == n and gy.size == n and gz.size == n
+    return _load().oracle_dot(float(kappa), float(theta), n, seed, counter_offset, seg, mode,
+                              _ptr(gx, ctypes.c_float), _ptr(gy, ctypes.c_float), _ptr(gz, ctypes.c_float))
 
 
 def num_threads():

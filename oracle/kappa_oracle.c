@@ -401,6 +401,58 @@ void oracle_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint
     out[1] = sum_t;
 }
 
+/* Indices j in [counter_offset, counter_offset + n) whose FP32-mode U1 takes
+ * the FP64 tail (1 - U1 < 2^-20), in increasing order; at most max_out are
+ * written.  Returns how many there are. */
+uint64_t oracle_find_tails(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg, uint64_t *out,
+                           uint64_t max_out)
+{
+    uint64_t found = 0;
+    const int64_t chunk = 1 << 20;
+    const int64_t nchunks = (int64_t)((n + (uint64_t)chunk - 1) / (uint64_t)chunk);
+    for (int64_t c0 = 0; c0 < nchunks; c0 += 64) {
+        uint64_t hits[64][16];
+        int counts[64] = {0};
+        int64_t c1 = c0 + 64 < nchunks ? c0 + 64 : nchunks;
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t c = c0; c < c1; ++c) {
+            uint64_t lo = (uint64_t)c * (uint64_t)chunk, hi = lo + (uint64_t)chunk;
+            if (hi > n) hi = n;
+            for (uint64_t j = lo; j < hi; ++j) {
+                uint32_t r[4];
+                particle_block(seed, counter_offset + j, seg, 0, r);
+                if ((r[0] >> 8) >= (1u << 24) - 16u && counts[c - c0] < 16)
+                    hits[c - c0][counts[c - c0]++] = counter_offset + j;
+            }
+        }
+        for (int64_t c = c0; c < c1; ++c)
+            for (int k = 0; k < counts[c - c0]; ++k) {
+                if (found < max_out) out[found] = hits[c - c0][k];
+                ++found;
+            }
+    }
+    return found;
+}
+
+/* Loss sum_i g_i . v_i of the samples (drift-free), for finite differences. */
+double oracle_dot(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg,
+                  int mode, const float *gx, const float *gy, const float *gz)
+{
+    double p[OP_COUNT];
+    double zero[3] = {0.0, 0.0, 0.0};
+    double sum = 0.0;
+    oracle_params(kappa, p);
+#pragma omp parallel for schedule(static) reduction(+ : sum)
+    for (int64_t j = 0; j < (int64_t)n; ++j) {
+        uint32_t r[4];
+        double v[3];
+        particle_block(seed, counter_offset + (uint64_t)j, seg, 0, r);
+        one_particle(p, theta, zero, mode, r, v);
+        sum += (double)gx[j] * v[0] + (double)gy[j] * v[1] + (double)gz[j] * v[2];
+    }
+    return sum;
+}
+
 /* Number of worker threads the oracle's parallel loops use. */
 int oracle_num_threads(void)
 {

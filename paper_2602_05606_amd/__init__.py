@@ -1,0 +1,283 @@
+"""Approximate Kappa velocity generator for MI355X (gfx950).
+
+Python binding of libkappa (include/kappa.h): an implementation of the
+inverse-transform Kappa sampler of Zenitani & Umeda, "An approximate Kappa
+generator for particle simulations" (arXiv 2602.05606, Table 1).  PyTorch is
+used only to allocate device memory and to supply the HIP stream; every step
+of the sampler runs in the library's HIP kernels.  There is no CPU fallback:
+the functions raise if the library is missing or the device is not gfx950.
+
+Precisions: FP64 (double outputs), FP32 (float outputs, FP32 bulk with an FP64
+inversion when 1 - U1 < 2^-20) and FP32_NOTAIL (diagnostics).
+"""
+import ctypes
+
+from . import _lib
+from ._lib import FP32, FP32_NOTAIL, FP64, KappaError, Segment
+
+__all__ = [
+    "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
+    "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
+    "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+def version():
+    return _lib.load().kappa_version().decode()
+
+
+def _dtype(precision):
+    torch = _torch()
+    return torch.float64 if precision == FP64 else torch.float32
+
+
+def _stream(stream, device):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def params(kappa):
+    """Setup rows of Table 1 for one species (host FP64): dict with kstar, a,
+    b, c, b_over_c, their kappa-derivatives da, db, dc, and lnbeta."""
+    out = (ctypes.c_double * len(_lib.PARAM_NAMES))()
+    _lib.check(_lib.load().kappa_params(float(kappa), out), "kappa_params")
+    return dict(zip(_lib.PARAM_NAMES, list(out)))
+
+
+def _outputs(n, precision, out, device):
+    torch = _torch()
+    if out is None:
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        return tuple(torch.empty(n, dtype=_dtype(precision), device=dev) for _ in range(3))
+    vx, vy, vz = out
+    for t in out:
+        if t.dtype != _dtype(precision) or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("out tensors must be contiguous CUDA tensors of the precision's dtype and >= n elements")
+    return vx, vy, vz
+
+
+def sample(kappa, theta, n, seed, *, counter_offset=0, seg_id=0, precision=FP32, out=None, device=None,
+           stream=None):
+    """Particles counter_offset .. counter_offset+n-1 of segment seg_id.
+    Returns (vx, vy, vz), device tensors (float64 for FP64, float32 otherwise)."""
+    vx, vy, vz = _outputs(n, precision, out, device)
+    st = _lib.load().kappa_sample(float(kappa), float(theta), n, seed, counter_offset, seg_id, precision,
+                                  _ptr(vx), _ptr(vy), _ptr(vz), _stream(stream, vx.device))
+    _lib.check(st, "kappa_sample")
+    return vx, vy, vz
+
+
+def backward_workspace_bytes(n):
+    return int(_lib.load().kappa_backward_workspace_bytes(n))
+
+
+def sample_backward(kappa, theta, n, seed, gx, gy, gz, *, counter_offset=0, seg_id=0, precision=FP32,
+                    workspace=None, stream=None):
+    """(dLoss/dkappa, dLoss/dtheta) through sample() at fixed uniforms, as a
+    float64 device tensor of 2 elements.  gx, gy, gz: upstream gradients."""
+    torch = _torch()
+    dev = gx.device
+    dt = _dtype(precision)
+    g = [t.contiguous() for t in (gx, gy, gz)]
+    for t in g:
+        if t.dtype != dt or t.numel() != n:
+            raise ValueError(f"upstream gradients must be {dt} with {n} elements")
+    wbytes = backward_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+    grad = torch.empty(2, dtype=torch.float64, device=dev)
+    st = _lib.load().kappa_sample_backward(float(kappa), float(theta), n, seed, counter_offset, seg_id, precision,
+                                           _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(grad), _ptr(workspace),
+                                           workspace.numel() * workspace.element_size(), _stream(stream, dev))
+    _lib.check(st, "kappa_sample_backward")
+    return grad
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class _KappaSample(torch.autograd.Function):
+        """v = KappaSample.apply(kappa, theta, n, seed, counter_offset, seg_id, precision)
+
+        kappa and theta are 0-d tensors; v is a (3, n) device tensor.  The
+        backward pass returns dLoss/dkappa and dLoss/dtheta through the
+        reparameterised sampler (the uniforms are fixed by seed and counters),
+        computed by the library's backward kernel."""
+
+        @staticmethod
+        def forward(ctx, kappa, theta, n, seed, counter_offset=0, seg_id=0, precision=FP32):
+            k, th = float(kappa), float(theta)
+            dev = kappa.device if kappa.is_cuda else torch.device("cuda", torch.cuda.current_device())
+            v = torch.empty((3, n), dtype=_dtype(precision), device=dev)
+            sample(k, th, n, seed, counter_offset=counter_offset, seg_id=seg_id, precision=precision,
+                   out=(v[0], v[1], v[2]))
+            ctx.args = (k, th, n, seed, counter_offset, seg_id, precision)
+            ctx.kappa_meta = (kappa.dtype, kappa.device, theta.dtype, theta.device)
+            return v
+
+        @staticmethod
+        def backward(ctx, gv):
+            k, th, n, seed, off, seg, prec = ctx.args
+            gv = gv.to(_dtype(prec)).contiguous()
+            grad = sample_backward(k, th, n, seed, gv[0], gv[1], gv[2], counter_offset=off, seg_id=seg,
+                                   precision=prec)
+            kd, kdev, td, tdev = ctx.kappa_meta
+            return (grad[0].to(dtype=kd, device=kdev), grad[1].to(dtype=td, device=tdev),
+                    None, None, None, None, None)
+
+    return _KappaSample
+
+
+KappaSample = _make_autograd()
+
+
+def philox(n, seed, counter_offset=0, seg_id=0, draw=0, device=None, stream=None):
+    """Raw Philox4x32-10 blocks as an (n, 4) int32 device tensor (the bits of
+    the uint32 words r0..r3)."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    out = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    st = _lib.load().kappa_philox(n, seed, counter_offset, seg_id, draw, _ptr(out), _stream(stream, dev))
+    _lib.check(st, "kappa_philox")
+    return out
+
+
+def _segments(segments):
+    """Builds a ctypes array of Segment from Segment objects or dicts/tuples
+    (kappa, theta, (dx, dy, dz), count, seg_id)."""
+    arr = (Segment * len(segments))()
+    for i, s in enumerate(segments):
+        if isinstance(s, Segment):
+            arr[i] = s
+            continue
+        if isinstance(s, dict):
+            kappa, theta, drift, count, seg_id = s["kappa"], s["theta"], s.get("drift", (0, 0, 0)), s["count"], s["seg_id"]
+        else:
+            kappa, theta, drift, count, seg_id = s
+        arr[i].kappa = float(kappa)
+        arr[i].theta = float(theta)
+        arr[i].drift[0], arr[i].drift[1], arr[i].drift[2] = (float(d) for d in drift)
+        arr[i].count = int(count)
+        arr[i].seg_id = int(seg_id)
+        arr[i].reserved = 0
+    return arr
+
+
+class Plan:
+    """A batched plan (kappa_plan): many (species, cell) segments laid out back
+    to back, sampled by one persistent kernel, optionally through a hipGraph."""
+
+    def __init__(self, segments, seed, precision=FP32):
+        self._segs = _segments(segments)
+        self.precision = precision
+        handle = ctypes.c_void_p()
+        st = _lib.load().kappa_plan_create(self._segs, len(self._segs), seed, precision, ctypes.byref(handle))
+        _lib.check(st, "kappa_plan_create")
+        self._h = handle
+        total = ctypes.c_uint64()
+        _lib.check(_lib.load().kappa_plan_total(self._h, ctypes.byref(total)), "kappa_plan_total")
+        self.total = total.value
+
+    def outputs(self, device=None):
+        return _outputs(self.total, self.precision, None, device)
+
+    def launch(self, out, stream=None):
+        vx, vy, vz = out
+        _lib.check(_lib.load().kappa_plan_launch(self._h, _ptr(vx), _ptr(vy), _ptr(vz), _stream(stream, vx.device)),
+                   "kappa_plan_launch")
+
+    def graph_launch(self, out, stream=None):
+        vx, vy, vz = out
+        _lib.check(_lib.load().kappa_plan_graph_launch(self._h, _ptr(vx), _ptr(vy), _ptr(vz),
+                                                       _stream(stream, vx.device)), "kappa_plan_graph_launch")
+
+    def autotune(self, out, reps=5, stream=None):
+        vx, vy, vz = out
+        _lib.check(_lib.load().kappa_plan_autotune(self._h, _ptr(vx), _ptr(vy), _ptr(vz), reps,
+                                                   _stream(stream, vx.device)), "kappa_plan_autotune")
+        return self.shape
+
+    @property
+    def shape(self):
+        b, u, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(_lib.load().kappa_plan_shape(self._h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(g)),
+                   "kappa_plan_shape")
+        return b.value, u.value, g.value
+
+    def set_shape(self, block, unroll, grid):
+        _lib.check(_lib.load().kappa_plan_set_shape(self._h, block, unroll, grid), "kappa_plan_set_shape")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().kappa_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sample_batched(segments, seed, precision=FP32, out=None, device=None, stream=None):
+    """One-shot batched sampling (kappa_sample_batched, synchronous)."""
+    segs = _segments(segments)
+    total = sum(int(s.count) for s in segs)
+    vx, vy, vz = _outputs(total, precision, out, device)
+    st = _lib.load().kappa_sample_batched(segs, len(segs), seed, precision, _ptr(vx), _ptr(vy), _ptr(vz),
+                                          _stream(stream, vx.device))
+    _lib.check(st, "kappa_sample_batched")
+    return vx, vy, vz
+
+
+def _exact(fn_name, kappa, theta, n, seed, precision, with_iters, out, device, stream):
+    torch = _torch()
+    vx, vy, vz = _outputs(n, precision, out, device)
+    iters = torch.empty(n, dtype=torch.int32, device=vx.device) if with_iters else None
+    st = getattr(_lib.load(), fn_name)(float(kappa), float(theta), n, seed, precision, _ptr(vx), _ptr(vy), _ptr(vz),
+                                       _ptr(iters), _stream(stream, vx.device))
+    _lib.check(st, fn_name)
+    return (vx, vy, vz, iters) if with_iters else (vx, vy, vz)
+
+
+def sample_exact_t(kappa, theta, n, seed, precision=FP32, with_iters=False, out=None, device=None, stream=None):
+    """Exact Kappa samples via 3 normals / sqrt(Gamma(kappa - 1/2)) (comparator)."""
+    return _exact("kappa_sample_exact_t", kappa, theta, n, seed, precision, with_iters, out, device, stream)
+
+
+def sample_exact_pareto(kappa, theta, n, seed, precision=FP32, with_iters=False, out=None, device=None, stream=None):
+    """Exact Kappa samples via Type II Pareto acceptance-rejection (comparator)."""
+    return _exact("kappa_sample_exact_pareto", kappa, theta, n, seed, precision, with_iters, out, device, stream)
+
+
+def fill_probe(n, precision, out, stream=None):
+    vx, vy, vz = out
+    _lib.check(_lib.load().kappa_fill_probe(n, precision, _ptr(vx), _ptr(vy), _ptr(vz), _stream(stream, vx.device)),
+               "kappa_fill_probe")
+
+
+def copy_probe(src, dst, stream=None):
+    nbytes = src.numel() * src.element_size()
+    _lib.check(_lib.load().kappa_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)),
+               "kappa_copy_probe")

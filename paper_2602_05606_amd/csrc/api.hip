@@ -1,0 +1,383 @@
+// api.hip -- the C ABI of libkappa (declared in include/kappa.h): argument
+// validation, device checks, error mapping and kernel dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "kappa_internal.hpp"
+
+extern "C" {
+kappa_status kappa_plan_create_impl(const kappa_segment *, uint32_t, uint64_t, int, kappa_plan *);
+kappa_status kappa_plan_launch_impl(kappa_plan, void *, void *, void *, void *);
+kappa_status kappa_plan_graph_launch_impl(kappa_plan, void *, void *, void *, void *);
+kappa_status kappa_plan_autotune_impl(kappa_plan, void *, void *, void *, int, void *);
+kappa_status kappa_plan_shape_impl(kappa_plan, int *, int *, int *);
+kappa_status kappa_plan_set_shape_impl(kappa_plan, int, int, int);
+kappa_status kappa_plan_total_impl(kappa_plan, uint64_t *);
+kappa_status kappa_plan_destroy_impl(kappa_plan);
+}
+
+namespace kappa {
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mutex;
+int g_dev_state[kMaxDevices] = {0};  // 0 unknown, 1 gfx950, -1 other
+int g_dev_cus[kMaxDevices] = {0};
+
+bool kappa_ok(double kappa) { return std::isfinite(kappa) && kappa > 1.5; }
+bool theta_ok(double theta) { return std::isfinite(theta) && theta > 0.0; }
+bool precision_ok(int p) { return p == KAPPA_FP64 || p == KAPPA_FP32 || p == KAPPA_FP32_NOTAIL; }
+size_t elem_size(int p) { return p == KAPPA_FP64 ? 8 : 4; }
+
+// Checks that the current device is gfx950 (cached per device).
+kappa_status require_device()
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return check_hip(err, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(KAPPA_EDEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (g_dev_state[dev] == 0) {
+        hipDeviceProp_t prop;
+        err = hipGetDeviceProperties(&prop, dev);
+        if (err != hipSuccess) return check_hip(err, "hipGetDeviceProperties");
+        g_dev_state[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+        g_dev_cus[dev] = prop.multiProcessorCount;
+        if (g_dev_state[dev] < 0)
+            return fail(KAPPA_EUNSUPPORTED, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    }
+    if (g_dev_state[dev] < 0) return fail(KAPPA_EUNSUPPORTED, "device %d is not gfx950", dev);
+    return KAPPA_OK;
+}
+
+kappa_status check_outputs(uint64_t n, int precision, void *vx, void *vy, void *vz)
+{
+    if (n == 0) return KAPPA_OK;
+    if (!vx || !vy || !vz) return fail(KAPPA_EINVAL, "null output pointer with n = %llu", (unsigned long long)n);
+    const size_t e = elem_size(precision);
+    if (reinterpret_cast<uintptr_t>(vx) % e || reinterpret_cast<uintptr_t>(vy) % e ||
+        reinterpret_cast<uintptr_t>(vz) % e)
+        return fail(KAPPA_EALIGN, "output pointers must be aligned to %zu bytes", e);
+    return KAPPA_OK;
+}
+
+bool vec_aligned(int precision, const void *vx, const void *vy, const void *vz)
+{
+    (void)precision;
+    return reinterpret_cast<uintptr_t>(vx) % 16 == 0 && reinterpret_cast<uintptr_t>(vy) % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(vz) % 16 == 0;
+}
+
+}  // namespace
+
+kappa_status fail(kappa_status status, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+kappa_status check_hip(hipError_t err, const char *what)
+{
+    if (err == hipSuccess) return KAPPA_OK;
+    return fail(KAPPA_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(err), static_cast<int>(err));
+}
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (g_dev_cus[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        g_dev_cus[dev] = cus;
+    }
+    return g_dev_cus[dev];
+}
+
+}  // namespace kappa
+
+using namespace kappa;
+
+extern "C" {
+
+const char *kappa_version(void) { return "libkappa 0.1.0 (gfx950)"; }
+
+const char *kappa_last_error(void) { return g_last_error; }
+
+const char *kappa_status_string(kappa_status status)
+{
+    switch (status) {
+    case KAPPA_OK: return "KAPPA_OK";
+    case KAPPA_EINVAL: return "KAPPA_EINVAL: invalid argument";
+    case KAPPA_EALIGN: return "KAPPA_EALIGN: misaligned pointer";
+    case KAPPA_EDEVICE: return "KAPPA_EDEVICE: HIP runtime error";
+    case KAPPA_ENOMEM: return "KAPPA_ENOMEM: device allocation failed";
+    case KAPPA_EUNSUPPORTED: return "KAPPA_EUNSUPPORTED: device is not gfx950";
+    case KAPPA_ERANGE: return "KAPPA_ERANGE: size out of range";
+    }
+    return "unknown kappa_status";
+}
+
+kappa_status kappa_params(double kappa, double *out)
+{
+    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!out) return fail(KAPPA_EINVAL, "null output array");
+    const Setup s = make_setup(kappa);
+    out[KAPPA_P_KSTAR] = s.kstar;
+    out[KAPPA_P_A] = s.a;
+    out[KAPPA_P_B] = s.b;
+    out[KAPPA_P_C] = s.c;
+    out[KAPPA_P_B_OVER_C] = s.b_over_c;
+    out[KAPPA_P_DA] = s.da;
+    out[KAPPA_P_DB] = s.db;
+    out[KAPPA_P_DC] = s.dc;
+    out[KAPPA_P_LNBETA] = s.lnbeta;
+    return KAPPA_OK;
+}
+
+kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                          uint32_t seg_id, int precision, void *vx, void *vy, void *vz, void *stream)
+{
+    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (n > 0 && counter_offset > UINT64_MAX - (n - 1))
+        return fail(KAPPA_EINVAL, "counter_offset + n exceeds 2^64");
+    kappa_status st = check_outputs(n, precision, vx, vy, vz);
+    if (st != KAPPA_OK || n == 0) return st;
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    const Setup s = make_setup(kappa);
+    FwdArgs a;
+    a.n = n;
+    a.counter_offset = counter_offset;
+    a.seg = seg_id;
+    a.k0 = static_cast<uint32_t>(seed);
+    a.k1 = static_cast<uint32_t>(seed >> 32);
+    a.vx = vx;
+    a.vy = vy;
+    a.vz = vz;
+    a.s64 = species_f64(s, theta);
+    a.s32 = species_f32(s, theta);
+    const bool vec = vec_aligned(precision, vx, vy, vz);
+    const Shape shape = forward_shape(precision, n, vec);
+    return check_hip(launch_forward(precision, shape, vec, a, static_cast<hipStream_t>(stream)), "forward kernel launch");
+}
+
+size_t kappa_backward_workspace_bytes(uint64_t n)
+{
+    const size_t bytes = static_cast<size_t>(backward_grid(n)) * 2 * sizeof(double);
+    return (bytes + 255) & ~static_cast<size_t>(255);
+}
+
+kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                                   uint32_t seg_id, int precision, const void *gx, const void *gy, const void *gz,
+                                   double *grad, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (!grad) return fail(KAPPA_EINVAL, "null grad pointer");
+    if (reinterpret_cast<uintptr_t>(grad) % 8) return fail(KAPPA_EALIGN, "grad must be 8-byte aligned");
+    if (n > 0 && counter_offset > UINT64_MAX - (n - 1))
+        return fail(KAPPA_EINVAL, "counter_offset + n exceeds 2^64");
+    if (n > 0 && (!gx || !gy || !gz)) return fail(KAPPA_EINVAL, "null gradient pointer with n > 0");
+    const size_t e = elem_size(precision);
+    if (n > 0 && (reinterpret_cast<uintptr_t>(gx) % e || reinterpret_cast<uintptr_t>(gy) % e ||
+                  reinterpret_cast<uintptr_t>(gz) % e))
+        return fail(KAPPA_EALIGN, "gradient pointers must be aligned to %zu bytes", e);
+    if (!workspace) return fail(KAPPA_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(KAPPA_EALIGN, "workspace must be 256-byte aligned");
+    if (workspace_bytes < kappa_backward_workspace_bytes(n))
+        return fail(KAPPA_ERANGE, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes,
+                    kappa_backward_workspace_bytes(n));
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    const Setup s = make_setup(kappa);
+    BwdArgs a;
+    a.n = n;
+    a.counter_offset = counter_offset;
+    a.seg = seg_id;
+    a.k0 = static_cast<uint32_t>(seed);
+    a.k1 = static_cast<uint32_t>(seed >> 32);
+    a.gx = gx;
+    a.gy = gy;
+    a.gz = gz;
+    a.partials = static_cast<double *>(workspace);
+    a.s64 = species_f64(s, theta);
+    a.s32 = species_f32(s, theta);
+    return check_hip(launch_backward(precision, a, grad, static_cast<hipStream_t>(stream)), "backward kernel launch");
+}
+
+kappa_status kappa_philox(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id, uint32_t draw,
+                          uint32_t *out, void *stream)
+{
+    if (n == 0) return KAPPA_OK;
+    if (!out) return fail(KAPPA_EINVAL, "null output pointer");
+    if (reinterpret_cast<uintptr_t>(out) % 16) return fail(KAPPA_EALIGN, "Philox output must be 16-byte aligned");
+    if (counter_offset > UINT64_MAX - (n - 1)) return fail(KAPPA_EINVAL, "counter_offset + n exceeds 2^64");
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_philox(n, counter_offset, seg_id, draw, static_cast<uint32_t>(seed),
+                                   static_cast<uint32_t>(seed >> 32), out, static_cast<hipStream_t>(stream)),
+                     "Philox kernel launch");
+}
+
+static kappa_status exact_common(double kappa, double theta, uint64_t n, int precision, void *vx, void *vy, void *vz,
+                                 uint32_t *iters)
+{
+    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
+    if (precision != KAPPA_FP64 && precision != KAPPA_FP32)
+        return fail(KAPPA_EINVAL, "exact generators take KAPPA_FP64 or KAPPA_FP32 (got %d)", precision);
+    kappa_status st = check_outputs(n, precision, vx, vy, vz);
+    if (st != KAPPA_OK) return st;
+    if (iters && reinterpret_cast<uintptr_t>(iters) % 4) return fail(KAPPA_EALIGN, "iters must be 4-byte aligned");
+    return KAPPA_OK;
+}
+
+kappa_status kappa_sample_exact_t(double kappa, double theta, uint64_t n, uint64_t seed, int precision, void *vx,
+                                  void *vy, void *vz, uint32_t *iters, void *stream)
+{
+    kappa_status st = exact_common(kappa, theta, n, precision, vx, vy, vz, iters);
+    if (st != KAPPA_OK || n == 0) return st;
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), vx, vy, vz, iters, kappa, theta};
+    return check_hip(launch_exact_t(precision, a, static_cast<hipStream_t>(stream)), "exact t kernel launch");
+}
+
+kappa_status kappa_sample_exact_pareto(double kappa, double theta, uint64_t n, uint64_t seed, int precision, void *vx,
+                                       void *vy, void *vz, uint32_t *iters, void *stream)
+{
+    kappa_status st = exact_common(kappa, theta, n, precision, vx, vy, vz, iters);
+    if (st != KAPPA_OK || n == 0) return st;
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), vx, vy, vz, iters, kappa, theta};
+    return check_hip(launch_exact_pareto(precision, a, static_cast<hipStream_t>(stream)), "exact Pareto kernel launch");
+}
+
+kappa_status kappa_fill_probe(uint64_t n, int precision, void *vx, void *vy, void *vz, void *stream)
+{
+    if (precision != KAPPA_FP64 && precision != KAPPA_FP32)
+        return fail(KAPPA_EINVAL, "fill probe takes KAPPA_FP64 or KAPPA_FP32 (got %d)", precision);
+    kappa_status st = check_outputs(n, precision, vx, vy, vz);
+    if (st != KAPPA_OK || n == 0) return st;
+    if (!vec_aligned(precision, vx, vy, vz)) return fail(KAPPA_EALIGN, "fill probe outputs must be 16-byte aligned");
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_fill_probe(precision, n, vx, vy, vz, static_cast<hipStream_t>(stream)), "fill probe launch");
+}
+
+kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t bytes, void *stream)
+{
+    if (bytes == 0) return KAPPA_OK;
+    if (!src || !dst) return fail(KAPPA_EINVAL, "null pointer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(KAPPA_EALIGN, "copy probe needs 16-byte aligned pointers and a size multiple of 16");
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_copy_probe(src, dst, bytes, static_cast<hipStream_t>(stream)), "copy probe launch");
+}
+
+// ---- batched --------------------------------------------------------------
+
+static kappa_status validate_segments(const kappa_segment *segs, uint32_t nseg, int precision)
+{
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (!segs) return fail(KAPPA_EINVAL, "null segment table");
+    if (nseg == 0 || nseg > KAPPA_MAX_SEGMENTS)
+        return fail(KAPPA_ERANGE, "segment count %u outside [1, %u]", nseg, KAPPA_MAX_SEGMENTS);
+    uint64_t total = 0;
+    for (uint32_t s = 0; s < nseg; ++s) {
+        const kappa_segment &g = segs[s];
+        if (!kappa_ok(g.kappa)) return fail(KAPPA_EINVAL, "segment %u: kappa must be finite and > 3/2", s);
+        if (!theta_ok(g.theta)) return fail(KAPPA_EINVAL, "segment %u: theta must be finite and > 0", s);
+        if (!std::isfinite(g.drift[0]) || !std::isfinite(g.drift[1]) || !std::isfinite(g.drift[2]))
+            return fail(KAPPA_EINVAL, "segment %u: drift must be finite", s);
+        if (g.reserved != 0) return fail(KAPPA_EINVAL, "segment %u: reserved field must be 0", s);
+        if (g.count > UINT64_MAX - total) return fail(KAPPA_ERANGE, "total particle count overflows");
+        total += g.count;
+    }
+    if (total / 1024 >= UINT32_MAX) return fail(KAPPA_ERANGE, "total particle count too large for the tile map");
+    return KAPPA_OK;
+}
+
+kappa_status kappa_plan_create(const kappa_segment *segs, uint32_t nseg, uint64_t seed, int precision, kappa_plan *out)
+{
+    if (!out) return fail(KAPPA_EINVAL, "null plan pointer");
+    *out = nullptr;
+    kappa_status st = validate_segments(segs, nseg, precision);
+    if (st != KAPPA_OK) return st;
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    return kappa_plan_create_impl(segs, nseg, seed, precision, out);
+}
+
+kappa_status kappa_plan_total(kappa_plan plan, uint64_t *total)
+{
+    if (!plan || !total) return fail(KAPPA_EINVAL, "null argument");
+    return kappa_plan_total_impl(plan, total);
+}
+
+kappa_status kappa_plan_launch(kappa_plan plan, void *vx, void *vy, void *vz, void *stream)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_launch_impl(plan, vx, vy, vz, stream);
+}
+
+kappa_status kappa_plan_graph_launch(kappa_plan plan, void *vx, void *vy, void *vz, void *stream)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_graph_launch_impl(plan, vx, vy, vz, stream);
+}
+
+kappa_status kappa_plan_autotune(kappa_plan plan, void *vx, void *vy, void *vz, int reps, void *stream)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    if (reps < 1) return fail(KAPPA_EINVAL, "reps must be >= 1");
+    return kappa_plan_autotune_impl(plan, vx, vy, vz, reps, stream);
+}
+
+kappa_status kappa_plan_shape(kappa_plan plan, int *block, int *unroll, int *grid)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_shape_impl(plan, block, unroll, grid);
+}
+
+kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int grid)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_set_shape_impl(plan, block, unroll, grid);
+}
+
+kappa_status kappa_plan_destroy(kappa_plan plan)
+{
+    if (!plan) return KAPPA_OK;
+    return kappa_plan_destroy_impl(plan);
+}
+
+kappa_status kappa_sample_batched(const kappa_segment *segs, uint32_t nseg, uint64_t seed, int precision, void *vx,
+                                  void *vy, void *vz, void *stream)
+{
+    kappa_plan plan = nullptr;
+    kappa_status st = kappa_plan_create(segs, nseg, seed, precision, &plan);
+    if (st != KAPPA_OK) return st;
+    st = kappa_plan_launch_impl(plan, vx, vy, vz, stream);
+    if (st == KAPPA_OK) st = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+    kappa_plan_destroy_impl(plan);
+    return st;
+}
+
+}  // extern "C"

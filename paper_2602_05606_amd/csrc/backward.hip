@@ -1,0 +1,247 @@
+// backward.hip -- reparameterisation gradient of the approximate Kappa
+// generator (Zenitani & Umeda, arXiv 2602.05606) with respect to kappa and
+// theta, at fixed uniforms.
+//
+// Per particle the kernel regenerates the Philox block, redoes the inversion
+// of Sec. 4, and differentiates it: v is linear in theta (Table 1), so
+// dv/dtheta = v/theta; x = (V/theta)^2 is the root of P(x) = b x^2 + (a+cL) x
+// + L (eq:v) with dP/dx = 2bx + a + cL = D, so dx/dkappa = -dP/dkappa / D with
+// dP/dkappa = b' x^2 + (a' + c'L + cL') x + L'; L = -kappa* expm1(z) with
+// z = -lT/kappa* and lT independent of kappa gives L' = -expm1(z) + z e^z;
+// then dv/dkappa = v (dx/dkappa) / (2x).
+//
+// The kernel reads the upstream gradient (3 x sizeof(T) bytes per particle)
+// and writes one pair of FP64 partial sums per block; a second one-block
+// kernel adds the partials in a fixed order.
+#include "kappa_device.hpp"
+#include "kappa_internal.hpp"
+
+namespace kappa {
+
+namespace {
+
+constexpr int kBwdBlock = 256;
+constexpr int kBwdMaxGrid = 4096;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Loads U consecutive values of T from p (aligned to U * sizeof(T) bytes, a
+// multiple of 16) with 16-byte loads.
+template <typename T, int U>
+__device__ __forceinline__ void load_group(const T *p, T (&v)[U])
+{
+    static_assert((U * sizeof(T)) % 16 == 0, "vector loads need 16-byte groups");
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int c = 0; c < U / 4; ++c) {
+            const float4 q = reinterpret_cast<const float4 *>(p)[c];
+            v[4 * c] = q.x;
+            v[4 * c + 1] = q.y;
+            v[4 * c + 2] = q.z;
+            v[4 * c + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < U / 2; ++c) {
+            const double2 q = reinterpret_cast<const double2 *>(p)[c];
+            v[2 * c] = q.x;
+            v[2 * c + 1] = q.y;
+        }
+    }
+}
+
+// d(v . g)/dkappa contribution in FP64 for one particle (FP64 mode, FP32 tail).
+__device__ __forceinline__ double dk_term_f64(const InvF64 &inv, const SpeciesF64 &s, double vg)
+{
+    const double ez = exp(inv.z);
+    const double dL = -expm1(inv.z) + inv.z * ez;
+    const double x = inv.x;
+    const double num = fma(s.db * x, x, fma(fma(s.dc, inv.L, s.da) + s.c * dL, x, dL));
+    return vg * (-num / inv.D) / (2.0 * x);
+}
+
+template <int MODE, int U, bool VEC>
+__global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
+{
+    using T = typename std::conditional<MODE == kModeF64, double, float>::type;
+    const T *gx = static_cast<const T *>(a.gx);
+    const T *gy = static_cast<const T *>(a.gy);
+    const T *gz = static_cast<const T *>(a.gz);
+    double acc_k = 0.0, acc_s = 0.0;
+    const uint64_t ngroups = (a.n + U - 1) / U;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t j0 = g * U;
+        T ux[U], uy[U], uz[U];
+        if (VEC && j0 + U <= a.n) {
+            load_group<T, U>(gx + j0, ux);
+            load_group<T, U>(gy + j0, uy);
+            load_group<T, U>(gz + j0, uz);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const bool in = j0 + k < a.n;
+                ux[k] = in ? gx[j0 + k] : T(0);
+                uy[k] = in ? gy[j0 + k] : T(0);
+                uz[k] = in ? gz[j0 + k] : T(0);
+            }
+        }
+        uint32_t tails = 0;
+        float tail_dot[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            tail_dot[k] = 0.0f;
+            const Block4 b = particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+            if constexpr (MODE == kModeF64) {
+                bool high;
+                double u;
+                speed_uniform_f64(b.r0, b.r3, high, u);
+                const InvF64 inv = invert_f64(high, u, a.s64);
+                const DirF64 d = direction_f64(b.r1, b.r2);
+                const double V = a.s64.theta * sqrt(inv.x);
+                const double vg = V * (d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k]);
+                acc_s += vg;
+                acc_k += dk_term_f64(inv, a.s64, vg);
+            } else {
+                bool high;
+                float u;
+                speed_uniform_f32(b.r0, high, u);
+                const InvF32 inv = invert_f32(high, u, a.s32);
+                const DirF32 d = direction_f32(b.r1, b.r2);
+                const float dot = d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k];
+                if (MODE == kModeF32 && __builtin_expect(in_fp64_tail(b.r0), 0)) {
+                    tail_dot[k] = dot;
+                    tails |= 1u << k;
+                } else {
+                    const float V = a.s32.theta * sqrtf(inv.x);
+                    const float vg = V * dot;
+                    const float ez = expf(inv.z);
+                    const float dL = -expm1f(inv.z) + inv.z * ez;
+                    const float x = inv.x;
+                    const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
+                    const float term = vg * (-num / inv.D) / (2.0f * x);
+                    acc_s += static_cast<double>(vg);
+                    acc_k += static_cast<double>(term);
+                }
+            }
+        }
+        if constexpr (MODE == kModeF32) {
+            // rare: 1 - U1 < 2^-20, the speed comes from the FP64 inversion
+            if (__builtin_expect(tails != 0, 0)) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if ((tails >> k) & 1u) {
+                        const Block4 b = particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+                        bool h64;
+                        double u64;
+                        speed_uniform_f64(b.r0, b.r3, h64, u64);
+                        const InvF64 i64 = invert_f64(h64, u64, a.s64);
+                        // the sampler's output speed is the FP64 speed rounded to float
+                        const double V = static_cast<double>(static_cast<float>(a.s64.theta * sqrt(i64.x)));
+                        const double vg = V * static_cast<double>(tail_dot[k]);
+                        acc_s += vg;
+                        acc_k += dk_term_f64(i64, a.s64, vg);
+                    }
+                }
+            }
+        }
+    }
+    // block reduction: waves, then LDS across the 4 waves, in a fixed order
+    __shared__ double red[2][kBwdBlock / 64];
+    acc_k = wave_sum(acc_k);
+    acc_s = wave_sum(acc_s);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = acc_k;
+        red[1][wave] = acc_s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sk = 0.0, ss = 0.0;
+        for (int w = 0; w < kBwdBlock / 64; ++w) {
+            sk += red[0][w];
+            ss += red[1][w];
+        }
+        a.partials[2 * blockIdx.x] = sk;
+        a.partials[2 * blockIdx.x + 1] = ss;
+    }
+}
+
+__global__ void __launch_bounds__(kBwdBlock) backward_finalize(const double *partials, int nblocks,
+                                                               double inv_theta, double *grad)
+{
+    double sk = 0.0, ss = 0.0;
+    for (int j = threadIdx.x; j < nblocks; j += kBwdBlock) {
+        sk += partials[2 * j];
+        ss += partials[2 * j + 1];
+    }
+    __shared__ double red[2][kBwdBlock];
+    red[0][threadIdx.x] = sk;
+    red[1][threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = kBwdBlock / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        grad[0] = red[0][0];
+        grad[1] = red[1][0] * inv_theta;
+    }
+}
+
+constexpr int unroll_for(int mode)
+{
+    return mode == kModeF64 ? 2 : 4;
+}
+
+template <int MODE>
+hipError_t launch_mode(const BwdArgs &a, bool vec, hipStream_t stream)
+{
+    constexpr int U = unroll_for(MODE);
+    const int grid = backward_grid(a.n);
+    if (vec)
+        hipLaunchKernelGGL((backward_kernel<MODE, U, true>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((backward_kernel<MODE, U, false>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Fixed for a given n (independent of the device) so the summation order, and
+// hence the result, is reproducible.
+int backward_grid(uint64_t n)
+{
+    const uint64_t per_block = static_cast<uint64_t>(kBwdBlock) * 4;
+    const uint64_t need = (n + per_block - 1) / per_block;
+    return static_cast<int>(need < 1 ? 1 : (need > kBwdMaxGrid ? kBwdMaxGrid : need));
+}
+
+hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStream_t stream)
+{
+    const size_t esz = mode == kModeF64 ? 8 : 4;
+    const bool vec = (reinterpret_cast<uintptr_t>(args.gx) % (esz * unroll_for(mode)) == 0) &&
+                     (reinterpret_cast<uintptr_t>(args.gy) % (esz * unroll_for(mode)) == 0) &&
+                     (reinterpret_cast<uintptr_t>(args.gz) % (esz * unroll_for(mode)) == 0);
+    hipError_t err;
+    switch (mode) {
+    case kModeF64: err = launch_mode<kModeF64>(args, vec, stream); break;
+    case kModeF32: err = launch_mode<kModeF32>(args, vec, stream); break;
+    case kModeF32NoTail: err = launch_mode<kModeF32NoTail>(args, vec, stream); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(backward_finalize, dim3(1), dim3(kBwdBlock), 0, stream, args.partials,
+                       backward_grid(args.n), 1.0 / args.s64.theta, grad);
+    return hipGetLastError();
+}
+
+}  // namespace kappa

@@ -1,0 +1,580 @@
+// batched.hip -- many species and cells in one persistent launch.
+//
+// A plan lays the segments out back to back (segment s owns output positions
+// start[s] .. start[s+1]-1) and keeps on the device: the segment boundaries,
+// each segment's Table 1 setup (computed once on the host, as the paper
+// prescribes) with its drift, and a tile -> first-segment map.  The
+// persistent kernel walks the particle range with a grid stride; each group
+// of U consecutive particles finds its segment by a binary search restricted
+// to its tile's segment range.  Particle j of segment s uses the counter
+// (j - start[s], seg_id[s]), so a segment's samples equal a single-species
+// call with the same seed and seg_id, whatever the launch shape.
+//
+// The launch can be captured once into a hipGraph and replayed; the shape
+// (block, particles per thread, grid) is chosen by a timing sweep.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kappa_device.hpp"
+#include "kappa_internal.hpp"
+
+namespace kappa {
+
+namespace {
+
+constexpr uint64_t kTile = 1024;  // particles per tile of the segment map
+
+struct alignas(16) SegF32 {
+    float kstar, inv_kstar, a, b, c, half_inv_b, theta, dx, dy, dz;
+    uint32_t seg_id, pad;
+};
+
+struct alignas(16) SegF64 {
+    double kstar, inv_kstar, a, b, c, half_inv_b, theta, dx, dy, dz;
+};
+
+struct BatchArgs {
+    uint64_t total;
+    uint32_t k0, k1;
+    uint32_t nseg;
+    const uint64_t *start;   // nseg + 1
+    const uint32_t *tile;    // ntiles + 1
+    const SegF32 *seg32;     // nseg
+    const SegF64 *seg64;     // nseg
+    const uint32_t *seg_ids; // nseg
+    void *vx, *vy, *vz;
+};
+
+// Largest s in [lo, hi] with start[s] <= j (start[lo] <= j holds).
+__device__ __forceinline__ uint32_t find_segment(const uint64_t *start, uint32_t lo, uint32_t hi, uint64_t j)
+{
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int U>
+__device__ __forceinline__ void store_group_b(T *p, const T (&v)[U])
+{
+    constexpr int kBytes = U * static_cast<int>(sizeof(T));
+    if constexpr (kBytes % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < kBytes / 16; ++c) {
+            if constexpr (sizeof(T) == 4)
+                reinterpret_cast<float4 *>(p)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+            else
+                reinterpret_cast<double2 *>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k) p[k] = v[k];
+    }
+}
+
+template <int MODE, int U>
+__global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
+{
+    using T = typename std::conditional<MODE == kModeF64, double, float>::type;
+    T *vx = static_cast<T *>(a.vx);
+    T *vy = static_cast<T *>(a.vy);
+    T *vz = static_cast<T *>(a.vz);
+    const uint64_t ngroups = (a.total + U - 1) / U;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t j0 = g * U;
+        const uint64_t t = j0 / kTile;
+        uint32_t s = find_segment(a.start, a.tile[t], a.tile[t + 1], j0);
+        T x[U], y[U], z[U];
+        uint32_t seg_of[U];
+        uint32_t tails = 0;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t j = j0 + k;
+            if (j >= a.total) {
+                x[k] = y[k] = z[k] = T(0);
+                seg_of[k] = s;
+                continue;
+            }
+            while (s + 1 < a.nseg && a.start[s + 1] <= j) ++s;
+            seg_of[k] = s;
+            const uint64_t local = j - a.start[s];
+            const Block4 b = particle_block(local, a.seg_ids[s], 0, a.k0, a.k1);
+            if constexpr (MODE == kModeF64) {
+                const SegF64 q = a.seg64[s];
+                SpeciesF64 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.half_inv_b, q.theta, 0, 0, 0};
+                particle_f64(b, sp, x[k], y[k], z[k]);
+                x[k] += q.dx;
+                y[k] += q.dy;
+                z[k] += q.dz;
+            } else {
+                const SegF32 q = a.seg32[s];
+                SpeciesF32 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.half_inv_b, q.theta, 0, 0, 0};
+                particle_f32(b, sp, x[k], y[k], z[k]);
+                x[k] += q.dx;
+                y[k] += q.dy;
+                z[k] += q.dz;
+                if constexpr (MODE == kModeF32) tails |= static_cast<uint32_t>(in_fp64_tail(b.r0)) << k;
+            }
+        }
+        if constexpr (MODE == kModeF32) {
+            if (__builtin_expect(tails != 0, 0)) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if ((tails >> k) & 1u) {
+                        const uint32_t q = seg_of[k];
+                        const SegF64 w = a.seg64[q];
+                        const SegF32 f = a.seg32[q];
+                        const SpeciesF64 s64{w.kstar, w.inv_kstar, w.a, w.b, w.c, w.half_inv_b, w.theta, 0, 0, 0};
+                        const Block4 b = particle_block(j0 + k - a.start[q], a.seg_ids[q], 0, a.k0, a.k1);
+                        tail_particle_f32(b, s64, x[k], y[k], z[k]);
+                        x[k] += f.dx;
+                        y[k] += f.dy;
+                        z[k] += f.dz;
+                    }
+                }
+            }
+        }
+        if (j0 + U <= a.total) {
+            store_group_b<T, U>(vx + j0, x);
+            store_group_b<T, U>(vy + j0, y);
+            store_group_b<T, U>(vz + j0, z);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (j0 + k < a.total) {
+                    vx[j0 + k] = x[k];
+                    vy[j0 + k] = y[k];
+                    vz[j0 + k] = z[k];
+                }
+            }
+        }
+    }
+}
+
+template <int MODE>
+hipError_t launch_batched_mode(const Shape &sh, const BatchArgs &a, hipStream_t stream)
+{
+    dim3 grid(sh.grid), block(sh.block);
+    switch (sh.unroll) {
+    case 1: hipLaunchKernelGGL((batched_kernel<MODE, 1>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((batched_kernel<MODE, 2>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((batched_kernel<MODE, 4>), grid, block, 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((batched_kernel<MODE, 8>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(int mode, const Shape &sh, const BatchArgs &a, hipStream_t stream)
+{
+    switch (mode) {
+    case kModeF64: return launch_batched_mode<kModeF64>(sh, a, stream);
+    case kModeF32: return launch_batched_mode<kModeF32>(sh, a, stream);
+    case kModeF32NoTail: return launch_batched_mode<kModeF32NoTail>(sh, a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool shape_valid(const Shape &s)
+{
+    const bool b = s.block == 64 || s.block == 128 || s.block == 256;
+    const bool u = s.unroll == 1 || s.unroll == 2 || s.unroll == 4 || s.unroll == 8;
+    return b && u && s.grid >= 1;
+}
+
+// ---- autotune cache: a flat JSON object {"key": "block,unroll,grid", ...} ----
+std::mutex g_cache_mutex;
+
+std::map<std::string, std::string> read_cache(const char *path)
+{
+    std::map<std::string, std::string> m;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return m;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    // parse "k": "v" pairs
+    size_t pos = 0;
+    while (true) {
+        size_t k0 = text.find('"', pos);
+        if (k0 == std::string::npos) break;
+        size_t k1 = text.find('"', k0 + 1);
+        size_t v0 = text.find('"', k1 + 1);
+        size_t v1 = v0 == std::string::npos ? v0 : text.find('"', v0 + 1);
+        if (k1 == std::string::npos || v1 == std::string::npos) break;
+        m[text.substr(k0 + 1, k1 - k0 - 1)] = text.substr(v0 + 1, v1 - v0 - 1);
+        pos = v1 + 1;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, std::string> &m)
+{
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : m) std::fprintf(f, "  \"%s\": \"%s\"%s\n", kv.first.c_str(), kv.second.c_str(), ++i < m.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+std::string cache_key(int mode, uint64_t total, uint32_t nseg)
+{
+    // bucket by powers of two of the total and the segment count
+    int tb = 0, sb = 0;
+    while ((1ull << tb) < total && tb < 63) ++tb;
+    while ((1u << sb) < nseg && sb < 31) ++sb;
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "batched|mode%d|total2^%d|nseg2^%d", mode, tb, sb);
+    return buf;
+}
+
+}  // namespace
+
+}  // namespace kappa
+
+struct kappa_plan_s {
+    int device = 0;
+    int mode = 0;
+    uint64_t total = 0;
+    uint32_t nseg = 0;
+    uint32_t k0 = 0, k1 = 0;
+    kappa::Shape shape{256, 4, 1};
+    void *dev_block = nullptr;  // one allocation holding every table
+    const uint64_t *start = nullptr;
+    const uint32_t *tile = nullptr;
+    const kappa::SegF32 *seg32 = nullptr;
+    const kappa::SegF64 *seg64 = nullptr;
+    const uint32_t *seg_ids = nullptr;
+    // captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    void *g_vx = nullptr, *g_vy = nullptr, *g_vz = nullptr;
+    kappa::Shape g_shape{0, 0, 0};
+};
+
+namespace kappa {
+
+namespace {
+
+BatchArgs batch_args(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+{
+    BatchArgs a;
+    a.total = p->total;
+    a.k0 = p->k0;
+    a.k1 = p->k1;
+    a.nseg = p->nseg;
+    a.start = p->start;
+    a.tile = p->tile;
+    a.seg32 = p->seg32;
+    a.seg64 = p->seg64;
+    a.seg_ids = p->seg_ids;
+    a.vx = vx;
+    a.vy = vy;
+    a.vz = vz;
+    return a;
+}
+
+Shape default_batched_shape(int mode, uint64_t total)
+{
+    Shape s;
+    s.block = 256;
+    s.unroll = mode == kModeF64 ? 2 : 4;
+    const uint64_t groups = (total + s.unroll - 1) / s.unroll;
+    const uint64_t need = (groups + s.block - 1) / s.block;
+    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 8;
+    s.grid = static_cast<int>(std::max<uint64_t>(1, std::min(need, cap)));
+    return s;
+}
+
+bool aligned_for(int mode, const Shape &s, void *vx, void *vy, void *vz)
+{
+    const size_t esz = mode == kModeF64 ? 8 : 4;
+    const size_t bytes = esz * s.unroll;
+    const size_t need = bytes >= 16 ? 16 : bytes;
+    return reinterpret_cast<uintptr_t>(vx) % need == 0 && reinterpret_cast<uintptr_t>(vy) % need == 0 &&
+           reinterpret_cast<uintptr_t>(vz) % need == 0;
+}
+
+// Shape actually launched: falls back to one particle per thread when the
+// outputs are not aligned for the group's vector store.
+Shape effective_shape(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+{
+    Shape s = p->shape;
+    if (!aligned_for(p->mode, s, vx, vy, vz)) s.unroll = 1;
+    return s;
+}
+
+void drop_graph(kappa_plan_s *p)
+{
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+}  // namespace
+
+}  // namespace kappa
+
+using namespace kappa;
+
+extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32_t nseg, uint64_t seed, int precision,
+                                               kappa_plan *out)
+{
+    auto *p = new (std::nothrow) kappa_plan_s();
+    if (!p) return fail(KAPPA_ENOMEM, "host allocation of the plan failed");
+    p->mode = precision;
+    p->nseg = nseg;
+    p->k0 = static_cast<uint32_t>(seed);
+    p->k1 = static_cast<uint32_t>(seed >> 32);
+    kappa_status st = check_hip(hipGetDevice(&p->device), "hipGetDevice");
+    if (st != KAPPA_OK) {
+        delete p;
+        return st;
+    }
+    // host tables
+    std::vector<uint64_t> start(nseg + 1);
+    std::vector<SegF32> s32(nseg);
+    std::vector<SegF64> s64(nseg);
+    std::vector<uint32_t> ids(nseg);
+    std::map<double, Setup> setups;  // species repeat across cells: set up each kappa once
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < nseg; ++s) {
+        start[s] = acc;
+        acc += segs[s].count;
+        auto it = setups.find(segs[s].kappa);
+        if (it == setups.end()) it = setups.emplace(segs[s].kappa, make_setup(segs[s].kappa)).first;
+        const SpeciesF64 a = species_f64(it->second, segs[s].theta);
+        const SpeciesF32 b = species_f32(it->second, segs[s].theta);
+        s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.half_inv_b, a.theta,
+                        segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
+        s32[s] = SegF32{b.kstar, b.inv_kstar, b.a, b.b, b.c, b.half_inv_b, b.theta,
+                        static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),
+                        static_cast<float>(segs[s].drift[2]), segs[s].seg_id, 0};
+        ids[s] = segs[s].seg_id;
+    }
+    start[nseg] = acc;
+    p->total = acc;
+    const uint64_t ntiles = (acc + kTile - 1) / kTile;
+    std::vector<uint32_t> tile(ntiles + 1);
+    {
+        uint32_t s = 0;
+        for (uint64_t t = 0; t <= ntiles; ++t) {
+            const uint64_t j = std::min<uint64_t>(t * kTile, acc > 0 ? acc - 1 : 0);
+            while (s + 1 < nseg && start[s + 1] <= j) ++s;
+            tile[t] = s;
+        }
+    }
+    // one device allocation: start | tile | seg32 | seg64 | ids, each 256-byte aligned
+    auto up = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    const size_t o_start = 0;
+    const size_t o_tile = o_start + up(start.size() * sizeof(uint64_t));
+    const size_t o_s32 = o_tile + up(tile.size() * sizeof(uint32_t));
+    const size_t o_s64 = o_s32 + up(s32.size() * sizeof(SegF32));
+    const size_t o_ids = o_s64 + up(s64.size() * sizeof(SegF64));
+    const size_t bytes = o_ids + up(ids.size() * sizeof(uint32_t));
+    if (hipMalloc(&p->dev_block, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(KAPPA_ENOMEM, "hipMalloc of %zu bytes for the plan tables failed", bytes);
+    }
+    std::vector<unsigned char> host(bytes, 0);
+    std::memcpy(host.data() + o_start, start.data(), start.size() * sizeof(uint64_t));
+    std::memcpy(host.data() + o_tile, tile.data(), tile.size() * sizeof(uint32_t));
+    std::memcpy(host.data() + o_s32, s32.data(), s32.size() * sizeof(SegF32));
+    std::memcpy(host.data() + o_s64, s64.data(), s64.size() * sizeof(SegF64));
+    std::memcpy(host.data() + o_ids, ids.data(), ids.size() * sizeof(uint32_t));
+    st = check_hip(hipMemcpy(p->dev_block, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy plan tables");
+    if (st != KAPPA_OK) {
+        hipFree(p->dev_block);
+        delete p;
+        return st;
+    }
+    auto *base = static_cast<unsigned char *>(p->dev_block);
+    p->start = reinterpret_cast<const uint64_t *>(base + o_start);
+    p->tile = reinterpret_cast<const uint32_t *>(base + o_tile);
+    p->seg32 = reinterpret_cast<const SegF32 *>(base + o_s32);
+    p->seg64 = reinterpret_cast<const SegF64 *>(base + o_s64);
+    p->seg_ids = reinterpret_cast<const uint32_t *>(base + o_ids);
+    p->shape = default_batched_shape(p->mode, p->total);
+    if (const char *path = std::getenv("KAPPA_AUTOTUNE_CACHE")) {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        auto m = read_cache(path);
+        auto it = m.find(cache_key(p->mode, p->total, p->nseg));
+        Shape s{};
+        if (it != m.end() && std::sscanf(it->second.c_str(), "%d,%d,%d", &s.block, &s.unroll, &s.grid) == 3 &&
+            shape_valid(s))
+            p->shape = s;
+    }
+    *out = p;
+    return KAPPA_OK;
+}
+
+namespace kappa {
+namespace {
+kappa_status check_plan_outputs(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+{
+    if (p->total == 0) return KAPPA_OK;
+    if (!vx || !vy || !vz) return fail(KAPPA_EINVAL, "null output pointer for a plan of %llu particles",
+                                       (unsigned long long)p->total);
+    const size_t e = p->mode == kModeF64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(vx) % e || reinterpret_cast<uintptr_t>(vy) % e ||
+        reinterpret_cast<uintptr_t>(vz) % e)
+        return fail(KAPPA_EALIGN, "output pointers must be aligned to %zu bytes", e);
+    return KAPPA_OK;
+}
+}  // namespace
+}  // namespace kappa
+
+extern "C" kappa_status kappa_plan_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+{
+    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    if (cs != KAPPA_OK || p->total == 0) return cs;
+    const Shape s = effective_shape(p, vx, vy, vz);
+    return check_hip(launch_batched(p->mode, s, batch_args(p, vx, vy, vz), static_cast<hipStream_t>(stream)),
+                     "batched kernel launch");
+}
+
+extern "C" kappa_status kappa_plan_graph_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+{
+    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    if (cs != KAPPA_OK || p->total == 0) return cs;
+    const Shape s = effective_shape(p, vx, vy, vz);
+    const bool stale = !p->exec || p->g_vx != vx || p->g_vy != vy || p->g_vz != vz || p->g_shape.block != s.block ||
+                       p->g_shape.unroll != s.unroll || p->g_shape.grid != s.grid;
+    if (stale) {
+        drop_graph(p);
+        kappa_status st;
+        if (!p->capture_stream) {
+            st = check_hip(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+            if (st != KAPPA_OK) return st;
+        }
+        st = check_hip(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (st != KAPPA_OK) return st;
+        const hipError_t le = launch_batched(p->mode, s, batch_args(p, vx, vy, vz), p->capture_stream);
+        const hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
+        if (le != hipSuccess) return check_hip(le, "batched kernel capture");
+        st = check_hip(ce, "hipStreamEndCapture");
+        if (st != KAPPA_OK) return st;
+        st = check_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if (st != KAPPA_OK) {
+            drop_graph(p);
+            return st;
+        }
+        p->g_vx = vx;
+        p->g_vy = vy;
+        p->g_vz = vz;
+        p->g_shape = s;
+    }
+    return check_hip(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *vy, void *vz, int reps, void *stream)
+{
+    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    if (cs != KAPPA_OK || p->total == 0) return cs;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    kappa_status s = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (s != KAPPA_OK) return s;
+    s = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    if (s != KAPPA_OK) {
+        hipEventDestroy(e0);
+        return s;
+    }
+    const int cus = device_cu_count();
+    const int blocks[] = {64, 128, 256};
+    const int unrolls[] = {1, 2, 4, 8};
+    const int per_cu[] = {1, 2, 4, 8, 16};
+    float best_ms = 1e30f;
+    Shape best = p->shape;
+    for (int b : blocks)
+        for (int u : unrolls)
+            for (int w : per_cu) {
+                Shape cand{b, u, w * cus};
+                const uint64_t groups = (p->total + u - 1) / u;
+                const uint64_t need = (groups + b - 1) / b;
+                if (static_cast<uint64_t>(cand.grid) > need && w > 1) continue;  // more blocks than work
+                if (!aligned_for(p->mode, cand, vx, vy, vz)) continue;
+                const BatchArgs a = batch_args(p, vx, vy, vz);
+                hipError_t err = launch_batched(p->mode, cand, a, st);  // warm-up
+                if (err != hipSuccess) {
+                    s = check_hip(err, "autotune launch");
+                    goto done;
+                }
+                hipEventRecord(e0, st);
+                for (int r = 0; r < reps; ++r) launch_batched(p->mode, cand, a, st);
+                hipEventRecord(e1, st);
+                s = check_hip(hipEventSynchronize(e1), "autotune synchronize");
+                if (s != KAPPA_OK) goto done;
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+    p->shape = best;
+    if (const char *path = std::getenv("KAPPA_AUTOTUNE_CACHE")) {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        auto m = read_cache(path);
+        char val[64];
+        std::snprintf(val, sizeof val, "%d,%d,%d", best.block, best.unroll, best.grid);
+        m[cache_key(p->mode, p->total, p->nseg)] = val;
+        write_cache(path, m);
+    }
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return s;
+}
+
+extern "C" kappa_status kappa_plan_shape_impl(kappa_plan p, int *block, int *unroll, int *grid)
+{
+    if (block) *block = p->shape.block;
+    if (unroll) *unroll = p->shape.unroll;
+    if (grid) *grid = p->shape.grid;
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_plan_set_shape_impl(kappa_plan p, int block, int unroll, int grid)
+{
+    const Shape s{block, unroll, grid};
+    if (!shape_valid(s)) return fail(KAPPA_EINVAL, "invalid launch shape (%d, %d, %d)", block, unroll, grid);
+    p->shape = s;
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_plan_total_impl(kappa_plan p, uint64_t *total)
+{
+    *total = p->total;
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_plan_destroy_impl(kappa_plan p)
+{
+    drop_graph(p);
+    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    if (p->dev_block) hipFree(p->dev_block);
+    delete p;
+    return KAPPA_OK;
+}

@@ -1,0 +1,218 @@
+// forward.hip -- single-species forward kernels of the approximate Kappa
+// generator (Table 1 of Zenitani & Umeda, arXiv 2602.05606) for gfx950, plus
+// the raw Philox dump and the store/copy measurement probes.
+//
+// The forward pass is a pure streaming write: 3 x sizeof(T) bytes per particle
+// and no reads.  Each thread produces `U` consecutive particles entirely in
+// registers and writes them with one 16-byte store per output array.
+#include "kappa_device.hpp"
+#include "kappa_internal.hpp"
+
+namespace kappa {
+
+// Stores U consecutive values of T at p (p aligned to U * sizeof(T) bytes
+// whenever U * sizeof(T) >= 16).
+template <typename T, int U>
+__device__ __forceinline__ void store_group(T *p, const T (&v)[U])
+{
+    constexpr int kBytes = U * static_cast<int>(sizeof(T));
+    if constexpr (kBytes % 16 == 0) {
+        constexpr int kPer = 16 / static_cast<int>(sizeof(T));
+#pragma unroll
+        for (int c = 0; c < U / kPer; ++c) {
+            if constexpr (sizeof(T) == 4) {
+                reinterpret_cast<float4 *>(p)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+            } else {
+                reinterpret_cast<double2 *>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+            }
+        }
+    } else if constexpr (kBytes == 8 && sizeof(T) == 4) {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k) p[k] = v[k];
+    }
+}
+
+template <int MODE, int U>
+__global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
+{
+    using T = typename std::conditional<MODE == kModeF64, double, float>::type;
+    T *vx = static_cast<T *>(a.vx);
+    T *vy = static_cast<T *>(a.vy);
+    T *vz = static_cast<T *>(a.vz);
+    const uint64_t ngroups = (a.n + U - 1) / U;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t j0 = g * U;
+        T x[U], y[U], z[U];
+        uint32_t tails = 0;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const Block4 b = particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+            if constexpr (MODE == kModeF64) {
+                particle_f64(b, a.s64, x[k], y[k], z[k]);
+            } else {
+                particle_f32(b, a.s32, x[k], y[k], z[k]);
+                if constexpr (MODE == kModeF32) tails |= static_cast<uint32_t>(in_fp64_tail(b.r0)) << k;
+            }
+        }
+        if constexpr (MODE == kModeF32) {
+            if (__builtin_expect(tails != 0, 0)) {
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if ((tails >> k) & 1u) {
+                        const Block4 b = particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+                        tail_particle_f32(b, a.s64, x[k], y[k], z[k]);
+                    }
+                }
+            }
+        }
+        if (j0 + U <= a.n) {
+            store_group<T, U>(vx + j0, x);
+            store_group<T, U>(vy + j0, y);
+            store_group<T, U>(vz + j0, z);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (j0 + k < a.n) {
+                    vx[j0 + k] = x[k];
+                    vy[j0 + k] = y[k];
+                    vz[j0 + k] = z[k];
+                }
+            }
+        }
+    }
+}
+
+namespace {
+
+template <int MODE>
+hipError_t launch_mode(const Shape &sh, const FwdArgs &a, hipStream_t stream)
+{
+    dim3 grid(sh.grid), block(sh.block);
+    switch (sh.unroll) {
+    case 1: hipLaunchKernelGGL((forward_kernel<MODE, 1>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((forward_kernel<MODE, 2>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((forward_kernel<MODE, 4>), grid, block, 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((forward_kernel<MODE, 8>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+Shape forward_shape(int mode, uint64_t n, bool vec)
+{
+    Shape s;
+    s.block = 256;
+    s.unroll = vec ? (mode == kModeF64 ? 2 : 4) : 1;
+    const uint64_t groups = (n + s.unroll - 1) / s.unroll;
+    const uint64_t need = (groups + s.block - 1) / s.block;
+    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 16;
+    s.grid = static_cast<int>(need < cap ? (need > 0 ? need : 1) : cap);
+    return s;
+}
+
+hipError_t launch_forward(int mode, const Shape &shape, bool vec, const FwdArgs &args, hipStream_t stream)
+{
+    Shape sh = shape;
+    if (!vec) sh.unroll = 1;
+    switch (mode) {
+    case kModeF64: return launch_mode<kModeF64>(sh, args, stream);
+    case kModeF32: return launch_mode<kModeF32>(sh, args, stream);
+    case kModeF32NoTail: return launch_mode<kModeF32NoTail>(sh, args, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Raw Philox dump: out[4j .. 4j+3] = block of particle counter_offset + j.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) philox_kernel(uint64_t n, uint64_t off, uint32_t seg, uint32_t draw,
+                                                     uint32_t k0, uint32_t k1, uint4 *out)
+{
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const Block4 b = particle_block(off + j, seg, draw, k0, k1);
+        out[j] = make_uint4(b.r0, b.r1, b.r2, b.r3);
+    }
+}
+
+hipError_t launch_philox(uint64_t n, uint64_t counter_offset, uint32_t seg, uint32_t draw, uint32_t k0, uint32_t k1,
+                         uint32_t *out, hipStream_t stream)
+{
+    const uint64_t need = (n + 255) / 256;
+    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 16;
+    const int grid = static_cast<int>(need < cap ? need : cap);
+    hipLaunchKernelGGL(philox_kernel, dim3(grid), dim3(256), 0, stream, n, counter_offset, seg, draw, k0, k1,
+                       reinterpret_cast<uint4 *>(out));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Store-only probe: the generator's store path with the arithmetic removed.
+// ---------------------------------------------------------------------------
+template <typename T, int U>
+__global__ void __launch_bounds__(256) fill_kernel(uint64_t n, T *vx, T *vy, T *vz)
+{
+    const uint64_t ngroups = (n + U - 1) / U;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t j0 = g * U;
+        T x[U], y[U], z[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            x[k] = T(1);
+            y[k] = T(2);
+            z[k] = T(3);
+        }
+        if (j0 + U <= n) {
+            store_group<T, U>(vx + j0, x);
+            store_group<T, U>(vy + j0, y);
+            store_group<T, U>(vz + j0, z);
+        } else {
+            for (int k = 0; k < U; ++k) {
+                if (j0 + k < n) {
+                    vx[j0 + k] = x[k];
+                    vy[j0 + k] = y[k];
+                    vz[j0 + k] = z[k];
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_fill_probe(int mode, uint64_t n, void *vx, void *vy, void *vz, hipStream_t stream)
+{
+    const Shape s = forward_shape(mode, n, true);
+    if (mode == kModeF64) {
+        hipLaunchKernelGGL((fill_kernel<double, 2>), dim3(s.grid), dim3(s.block), 0, stream, n,
+                           static_cast<double *>(vx), static_cast<double *>(vy), static_cast<double *>(vz));
+    } else {
+        hipLaunchKernelGGL((fill_kernel<float, 4>), dim3(s.grid), dim3(s.block), 0, stream, n,
+                           static_cast<float *>(vx), static_cast<float *>(vy), static_cast<float *>(vz));
+    }
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(const float4 *src, float4 *dst, uint64_t n16)
+{
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n16; j += stride)
+        dst[j] = src[j];
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t stream)
+{
+    const uint64_t n16 = bytes / 16;
+    const uint64_t need = (n16 + 255) / 256;
+    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 16;
+    const int grid = static_cast<int>(need < cap ? (need > 0 ? need : 1) : cap);
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, static_cast<const float4 *>(src),
+                       static_cast<float4 *>(dst), n16);
+    return hipGetLastError();
+}
+
+}  // namespace kappa

@@ -1,0 +1,77 @@
+// kappa_internal.hpp -- host-side declarations shared by the library's
+// translation units (launchers, launch shapes, error reporting).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/kappa.h"
+#include "kappa_params.hpp"
+
+namespace kappa {
+
+enum Mode { kModeF64 = KAPPA_FP64, kModeF32 = KAPPA_FP32, kModeF32NoTail = KAPPA_FP32_NOTAIL };
+
+// Launch shape: threads per block, particles per thread, blocks in the grid
+// (the kernels loop over their work with a grid stride, so any grid >= 1 is
+// valid and the output never depends on the shape).
+struct Shape {
+    int block;
+    int unroll;
+    int grid;
+};
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// Records a message for kappa_last_error() and returns status.
+kappa_status fail(kappa_status status, const char *fmt, ...);
+
+// Maps a HIP error to KAPPA_EDEVICE with its message (KAPPA_OK on hipSuccess).
+kappa_status check_hip(hipError_t err, const char *what);
+
+// ---- forward --------------------------------------------------------------
+struct FwdArgs {
+    uint64_t n;
+    uint64_t counter_offset;
+    uint32_t seg, k0, k1;
+    void *vx, *vy, *vz;
+    SpeciesF64 s64;
+    SpeciesF32 s32;
+};
+
+// Default shape for n particles in a mode; `vec` selects the vector-store path.
+Shape forward_shape(int mode, uint64_t n, bool vec);
+hipError_t launch_forward(int mode, const Shape &shape, bool vec, const FwdArgs &args, hipStream_t stream);
+hipError_t launch_philox(uint64_t n, uint64_t counter_offset, uint32_t seg, uint32_t draw, uint32_t k0, uint32_t k1,
+                         uint32_t *out, hipStream_t stream);
+hipError_t launch_fill_probe(int mode, uint64_t n, void *vx, void *vy, void *vz, hipStream_t stream);
+hipError_t launch_copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+
+// ---- backward -------------------------------------------------------------
+struct BwdArgs {
+    uint64_t n;
+    uint64_t counter_offset;
+    uint32_t seg, k0, k1;
+    const void *gx, *gy, *gz;
+    double *partials;  // 2 doubles per block
+    SpeciesF64 s64;
+    SpeciesF32 s32;
+};
+
+int backward_grid(uint64_t n);  // number of partial blocks for n particles
+hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStream_t stream);
+
+// ---- exact baselines ------------------------------------------------------
+struct ExactArgs {
+    uint64_t n;
+    uint32_t k0, k1;
+    void *vx, *vy, *vz;
+    uint32_t *iters;
+    double kappa, theta;
+};
+hipError_t launch_exact_t(int mode, const ExactArgs &args, hipStream_t stream);
+hipError_t launch_exact_pareto(int mode, const ExactArgs &args, hipStream_t stream);
+
+}  // namespace kappa

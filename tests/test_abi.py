@@ -1,0 +1,151 @@
+"""The C ABI on the CPU: the library loads, exports every entry point the
+header declares, computes the Table 1 setup like the oracle, and rejects bad
+arguments with the documented codes before any HIP call (so no GPU is needed).
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2602_05606_amd as kp
+from paper_2602_05606_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kappa.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"KAPPA_API\s+[\w\s\*]*?\b(kappa_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("kappa_sample", "kappa_sample_batched", "kappa_sample_backward"):
+        assert required in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    # and the binding's table covers the header exactly
+    assert set(_lib.SIGNATURES) == set(declared_symbols())
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in kp.version()
+    lib = _lib.load()
+    for code in range(7):
+        assert lib.kappa_status_string(code).decode().startswith("KAPPA_")
+
+
+@pytest.mark.parametrize("kappa", [1.5000001, 1.6, 2.0, 2.5, 3.0, 4.1, 7.5, 10.0, 15.0, 1e4])
+def test_setup_matches_oracle(orc, kappa):
+    got, ref = kp.params(kappa), orc.params(kappa)
+    # c (eq:c) is a ratio of two quadratics whose denominator nearly cancels
+    # near kappa = 4: its rounding error scales with the condition number of
+    # the two sums, which the tolerance of c and b = (b/c) c carries.
+    k = kappa
+    cond_c = ((0.123 * k * k + 1.12 * k + 2.56) / abs(0.123 * k * k - 1.12 * k + 2.56)
+              + (k * k + 7.89 * k + 15.6) / abs(k * k - 7.89 * k + 15.6))
+    eps = 2.0 ** -52
+    for name in ("kstar", "a", "b", "c", "b_over_c", "lnbeta"):
+        tol = 8 * eps * (cond_c if name in ("b", "c") else 4.0)
+        assert abs(got[name] - ref[name]) <= tol * abs(ref[name]) + 1e-300, name
+    for name in ("da", "db", "dc"):
+        assert abs(got[name] - ref[name]) <= 1e-12 * max(1.0, abs(ref[name])), name
+
+
+FAKE = ctypes.c_void_p(0x10000)        # never dereferenced: validation fails first
+FAKE_ODD = ctypes.c_void_p(0x10001)
+
+
+@pytest.mark.parametrize("kappa,theta,prec,code", [
+    (1.5, 1.0, 1, _lib.EINVAL), (1.0, 1.0, 1, _lib.EINVAL), (math.nan, 1.0, 1, _lib.EINVAL),
+    (math.inf, 1.0, 1, _lib.EINVAL), (3.0, 0.0, 1, _lib.EINVAL), (3.0, -1.0, 1, _lib.EINVAL),
+    (3.0, math.nan, 1, _lib.EINVAL), (3.0, 1.0, 7, _lib.EINVAL), (3.0, 1.0, -1, _lib.EINVAL),
+])
+def test_sample_rejects_bad_arguments(kappa, theta, prec, code):
+    lib = _lib.load()
+    assert lib.kappa_sample(kappa, theta, 10, 0, 0, 0, prec, FAKE, FAKE, FAKE, None) == code
+    assert lib.kappa_last_error()
+
+
+def test_sample_pointer_checks():
+    lib = _lib.load()
+    null = ctypes.c_void_p(0)
+    assert lib.kappa_sample(3.0, 1.0, 10, 0, 0, 0, 1, null, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_sample(3.0, 1.0, 10, 0, 0, 0, 1, FAKE_ODD, FAKE, FAKE, None) == _lib.EALIGN
+    assert lib.kappa_sample(3.0, 1.0, 10, 0, 0, 0, 0, ctypes.c_void_p(0x10004), FAKE, FAKE, None) == _lib.EALIGN
+    # n = 0 is a no-op, even with null pointers
+    assert lib.kappa_sample(3.0, 1.0, 0, 0, 0, 0, 1, null, null, null, None) == _lib.OK
+    # counter range overflow
+    assert lib.kappa_sample(3.0, 1.0, 10, 0, (1 << 64) - 5, 0, 1, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+
+
+def test_backward_argument_checks():
+    lib = _lib.load()
+    n = 1000
+    need = lib.kappa_backward_workspace_bytes(n)
+    assert need >= 16 and need % 256 == 0
+    assert lib.kappa_backward_workspace_bytes(0) >= 16
+    args = (3.0, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE)
+    assert lib.kappa_sample_backward(*args, FAKE, need - 1, None) == _lib.ERANGE
+    assert lib.kappa_sample_backward(*args, ctypes.c_void_p(0x10010), need, None) == _lib.EALIGN
+    assert lib.kappa_sample_backward(*args, None, need, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward(3.0, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, None, FAKE, need, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward(1.2, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, need, None) == _lib.EINVAL
+
+
+def test_plan_argument_checks():
+    lib = _lib.load()
+    good = kp._segments([(3.0, 1.0, (0, 0, 0), 10, 0)])
+    h = ctypes.c_void_p()
+    assert lib.kappa_plan_create(good, 0, 0, 1, ctypes.byref(h)) == _lib.ERANGE
+    assert lib.kappa_plan_create(None, 1, 0, 1, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.kappa_plan_create(good, 1, 0, 9, ctypes.byref(h)) == _lib.EINVAL
+    for bad in ([(1.4, 1.0, (0, 0, 0), 10, 0)], [(3.0, 0.0, (0, 0, 0), 10, 0)],
+                [(3.0, 1.0, (math.nan, 0, 0), 10, 0)]):
+        assert lib.kappa_plan_create(kp._segments(bad), 1, 0, 1, ctypes.byref(h)) == _lib.EINVAL
+    seg = kp._segments([(3.0, 1.0, (0, 0, 0), 10, 0)])
+    seg[0].reserved = 1
+    assert lib.kappa_plan_create(seg, 1, 0, 1, ctypes.byref(h)) == _lib.EINVAL
+    over = kp._segments([(3.0, 1.0, (0, 0, 0), (1 << 64) - 1, 0), (3.0, 1.0, (0, 0, 0), 5, 1)])
+    assert lib.kappa_plan_create(over, 2, 0, 1, ctypes.byref(h)) == _lib.ERANGE
+    assert lib.kappa_plan_destroy(None) == _lib.OK
+    assert lib.kappa_plan_launch(None, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+
+
+def test_exact_and_probe_argument_checks():
+    lib = _lib.load()
+    assert lib.kappa_sample_exact_t(1.5, 1.0, 10, 0, 1, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_exact_pareto(3.0, 1.0, 10, 0, 2, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_exact_t(3.0, 1.0, 10, 0, 1, FAKE, FAKE, FAKE, ctypes.c_void_p(0x10002), None) == _lib.EALIGN
+    assert lib.kappa_fill_probe(10, 1, FAKE, FAKE, ctypes.c_void_p(0x10004), None) == _lib.EALIGN
+    assert lib.kappa_copy_probe(FAKE, FAKE, 15, None) == _lib.EALIGN
+    assert lib.kappa_philox(4, 0, 0, 0, 0, ctypes.c_void_p(0x10004), None) == _lib.EALIGN
+    assert lib.kappa_philox(0, 0, 0, 0, 0, None, None) == _lib.OK
+
+
+def test_segment_struct_layout():
+    assert ctypes.sizeof(_lib.Segment) == 56
+
+
+def test_workload_tables_shapes():
+    import workloads
+    segs = workloads.batched_segments()
+    assert len(segs) == 4096 * 3
+    counts = np.array([s["count"] for s in segs])
+    assert counts.min() >= 1 and counts.max() <= 8192
+    # mean of the clipped lognormal (mu = ln 256, sigma = 1) is about 256 e^{1/2} = 422
+    assert 400 < counts.mean() < 445
+    kappas = sorted({s["kappa"] for s in segs})
+    assert len(kappas) == 3 and all(1.6 <= k <= 10 for k in kappas)
+    assert [s["seg_id"] for s in segs] == list(range(len(segs)))
+    chunks = workloads.c5_chunks()
+    assert sum(c for _, c in chunks) == 10 ** 9 and len(chunks) == 4

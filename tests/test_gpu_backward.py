@@ -1,0 +1,102 @@
+"""GPU parity of the reparameterisation backward pass.
+
+dLoss/dkappa and dLoss/dtheta from the library's backward kernel, against
+  * the oracle's FP64 adjoint at the same (mode's) uniforms;
+  * central finite differences (h = 1e-4) of the oracle's FP64 loss
+    sum_i g_i . v_i;
+  * torch.autograd through KappaSample.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_05606_amd as kp
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+MODE = {kp.FP64: 0, kp.FP32: 1, kp.FP32_NOTAIL: 2}
+
+
+def gpu_grad(kappa, theta, n, seed, g, precision, counter_offset=0):
+    dt = torch.float64 if precision == kp.FP64 else torch.float32
+    gt = [torch.from_numpy(np.ascontiguousarray(g[i])).to(dt).cuda() for i in range(3)]
+    out = kp.sample_backward(kappa, theta, n, seed, *gt, counter_offset=counter_offset, precision=precision)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_c3_full_size_against_oracle_adjoint(orc):
+    """C3: 2^26 particles, kappa 2.5, theta 1.3, FP32 + FP64 tail, g ~ N(0,1)."""
+    c = workloads.C3
+    g = workloads.upstream_gradient(c["n"])
+    got = gpu_grad(c["kappa"], c["theta"], c["n"], c["seed"], g, kp.FP32)
+    ref = orc.backward(c["kappa"], c["theta"], c["n"], c["seed"], g[0], g[1], g[2], mode=1)
+    rk, rt = abs(got[0] / ref[0] - 1), abs(got[1] / ref[1] - 1)
+    print(f"C3 dL/dkappa gpu {got[0]:.10e} oracle {ref[0]:.10e} rel {rk:.2e}; "
+          f"dL/dtheta gpu {got[1]:.10e} oracle {ref[1]:.10e} rel {rt:.2e}")
+    assert rk < 1e-5 and rt < 1e-5
+
+
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
+@pytest.mark.parametrize("kappa,theta", [(2.5, 1.3), (1.6, 1.0), (4.1, 0.8), (10.0, 2.0)])
+def test_against_finite_differences(orc, precision, kappa, theta):
+    n = 1 << 21
+    g = workloads.upstream_gradient(n, seed=21)
+    got = gpu_grad(kappa, theta, n, 8, g, precision)
+    mode = MODE[precision]
+    h = 1e-4
+    fd_k = (orc.dot(kappa + h, theta, n, 8, *g, mode=mode) - orc.dot(kappa - h, theta, n, 8, *g, mode=mode)) / (2 * h)
+    fd_t = (orc.dot(kappa, theta + h, n, 8, *g, mode=mode) - orc.dot(kappa, theta - h, n, 8, *g, mode=mode)) / (2 * h)
+    adj = orc.backward(kappa, theta, n, 8, *g, mode=mode)
+    tol = 1e-9 if precision == kp.FP64 else 2e-5
+    print(f"kappa {kappa} prec {precision}: dk gpu {got[0]:.9e} fd {fd_k:.9e} adj {adj[0]:.9e}; "
+          f"dt gpu {got[1]:.9e} fd {fd_t:.9e}")
+    assert abs(adj[0] / fd_k - 1) < 1e-6  # the oracle's adjoint agrees with its own differences
+    assert abs(got[0] / adj[0] - 1) < tol and abs(got[1] / adj[1] - 1) < tol
+    assert abs(got[0] / fd_k - 1) < max(tol, 1e-6) and abs(got[1] / fd_t - 1) < max(tol, 1e-6)
+
+
+def test_ragged_sizes_and_offsets(orc):
+    for n in (1, 5, 1000, 4097, 123457):
+        g = workloads.upstream_gradient(n, seed=n)
+        for precision in (kp.FP64, kp.FP32):
+            got = gpu_grad(3.0, 1.0, n, 4, g, precision, counter_offset=77)
+            ref = orc.backward(3.0, 1.0, n, 4, *g, counter_offset=77, mode=MODE[precision])
+            tol = 1e-10 if precision == kp.FP64 else 1e-4
+            for a, b in zip(got, ref):
+                assert abs(a - b) <= tol * (abs(b) + np.sqrt(n) * 1e-3), (n, precision, got, ref)
+
+
+def test_zero_particles_gives_zero():
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = kp.sample_backward(3.0, 1.0, 0, 0, e, e, e, precision=kp.FP32)
+    torch.cuda.synchronize()
+    assert out.cpu().tolist() == [0.0, 0.0]
+
+
+def test_fp32_tail_particles_in_backward(orc):
+    """Single tail particles: the backward takes the FP64 branch.  The upstream
+    gradient points along the particle's velocity, so g . v has no cancellation
+    and the FP32 bar (relative to the velocity's norm) applies to the result."""
+    tails = orc.find_tails(1 << 24, 12)
+    for j in tails[:4]:
+        v = orc.sample(1.6, 1.0, 1, 12, counter_offset=int(j), mode=1)[:3]
+        g = (np.array(v).reshape(3, 1) / np.linalg.norm(v)).astype(np.float32)
+        got = gpu_grad(1.6, 1.0, 1, 12, g, kp.FP32, counter_offset=int(j))
+        ref = orc.backward(1.6, 1.0, 1, 12, *g, counter_offset=int(j), mode=1)
+        assert abs(got[0] / ref[0] - 1) < 1e-5 and abs(got[1] / ref[1] - 1) < 1e-5
+
+
+def test_autograd_function(orc):
+    n = 200_000
+    kappa = torch.tensor(3.0, dtype=torch.float64, requires_grad=True)
+    theta = torch.tensor(1.2, dtype=torch.float64, requires_grad=True)
+    v = kp.KappaSample.apply(kappa, theta, n, 13, 0, 0, kp.FP64)
+    g = workloads.upstream_gradient(n, seed=99)
+    gt = torch.from_numpy(g.astype(np.float64)).cuda()
+    loss = (v * gt).sum()
+    loss.backward()
+    ref = orc.backward(3.0, 1.2, n, 13, *g, mode=0)
+    assert abs(kappa.grad.item() / ref[0] - 1) < 1e-9
+    assert abs(theta.grad.item() / ref[1] - 1) < 1e-9

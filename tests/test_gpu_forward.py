@@ -1,0 +1,155 @@
+"""GPU parity of the forward generator (Table 1) against the FP64 oracle.
+
+Every call goes through the C ABI of libkappa.  Bars:
+  * Philox words: bit-exact;
+  * velocities: per-particle norm-relative error <= 1e-13 (FP64) and 4e-6
+    (FP32, against the oracle evaluated at the FP32 mode's uniforms);
+  * determinism, chunking and store-path invariance: bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_05606_amd as kp
+import workloads
+from gpu_helpers import TOL_FP32, TOL_FP64, bits_equal, norm_rel_err, to_host
+
+pytestmark = pytest.mark.gpu
+
+MODE = {kp.FP64: 0, kp.FP32: 1, kp.FP32_NOTAIL: 2}
+
+
+def gpu_sample(kappa, theta, n, seed, precision, counter_offset=0, seg_id=0):
+    v = kp.sample(kappa, theta, n, seed, counter_offset=counter_offset, seg_id=seg_id, precision=precision)
+    torch.cuda.synchronize()
+    return v
+
+
+@pytest.mark.parametrize("seed,offset,seg,draw,n", [
+    (0, 0, 0, 0, 100_003),
+    (1, (1 << 32) - 1000, 0, 0, 5000),
+    (0x0123456789ABCDEF, 1 << 40, 12287, 3, 777),
+    ((1 << 64) - 1, 17, (1 << 32) - 1, (1 << 32) - 1, 64),
+])
+def test_philox_bit_exact(orc, seed, offset, seg, draw, n):
+    got = kp.philox(n, seed, counter_offset=offset, seg_id=seg, draw=draw).cpu().numpy().view(np.uint32)
+    ref = orc.philox_blocks(n, seed, counter_offset=offset, seg=seg, draw=draw)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_c1_plain_fp64_full(orc):
+    """C1 at its full size: 1e6 particles, kappa 3, theta 1, FP64, seed 0."""
+    c = workloads.C1
+    g = to_host(*gpu_sample(c["kappa"], c["theta"], c["n"], c["seed"], kp.FP64))
+    r = orc.sample(c["kappa"], c["theta"], c["n"], c["seed"], mode=0)[:3]
+    err = norm_rel_err(g, r)
+    print(f"C1 FP64 max norm-relative error {err:.3e}")
+    assert err <= TOL_FP64
+
+
+@pytest.mark.parametrize("kappa", [1.6, 2.5, 4.1, 10.0, 25.0])
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32, kp.FP32_NOTAIL])
+def test_forward_parity_ragged(orc, kappa, precision):
+    n = 1_000_003  # several tiles and a ragged tail
+    g = to_host(*gpu_sample(kappa, 1.7, n, 11, precision, counter_offset=123))
+    r = orc.sample(kappa, 1.7, n, 11, counter_offset=123, mode=MODE[precision])[:3]
+    err = norm_rel_err(g, r)
+    print(f"kappa {kappa} precision {precision}: max norm-relative error {err:.3e}")
+    assert err <= (TOL_FP64 if precision == kp.FP64 else TOL_FP32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 63, 64, 65, 1023, 4097])
+def test_small_and_ragged_sizes(orc, n):
+    for precision in (kp.FP64, kp.FP32):
+        g = to_host(*gpu_sample(3.0, 1.0, n, 5, precision, counter_offset=9))
+        r = orc.sample(3.0, 1.0, n, 5, counter_offset=9, mode=MODE[precision])[:3]
+        assert norm_rel_err(g, r) <= (TOL_FP64 if precision == kp.FP64 else TOL_FP32)
+
+
+def test_fp32_tail_particles(orc):
+    """Particles whose 1 - U1 < 2^-20 take the FP64 inversion in FP32 mode."""
+    n, seed = 1 << 24, 12
+    tails = orc.find_tails(n, seed)
+    assert len(tails) >= 5
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([tails, rng.integers(0, n, size=20000).astype(np.uint64)])
+    for kappa in (1.6, 3.0, 10.0):
+        v = gpu_sample(kappa, 1.0, n, seed, kp.FP32)
+        it = torch.from_numpy(idx.astype(np.int64)).cuda()
+        g = to_host(*(t[it] for t in v))
+        r = orc.sample_indices(kappa, 1.0, idx, seed, mode=1)
+        err_tail = norm_rel_err(tuple(a[:len(tails)] for a in g), tuple(a[:len(tails)] for a in r))
+        err_all = norm_rel_err(g, r)
+        print(f"kappa {kappa}: tail particles {len(tails)}, max error tail {err_tail:.3e}, sample {err_all:.3e}")
+        assert err_tail <= TOL_FP32 and err_all <= TOL_FP32
+        # the tail speeds are the largest of the run
+        speed = torch.sqrt(v[0].double() ** 2 + v[1].double() ** 2 + v[2].double() ** 2)
+        assert float(speed[torch.from_numpy(tails.astype(np.int64)).cuda()].min()) > float(torch.quantile(speed[:1 << 20], 0.999))
+
+
+@pytest.mark.parametrize("kappa", workloads.C2["kappas"])
+@pytest.mark.parametrize("precision", [kp.FP32, kp.FP64])
+def test_c2_full_size_sampled(orc, kappa, precision):
+    """C2 at full size (1e8 particles, seed 1) in the benchmark's launch
+    configuration, checked on 20000 random particles and every tail particle."""
+    c = workloads.C2
+    n = c["n"]
+    v = gpu_sample(kappa, c["theta"], n, c["seed"], precision)
+    rng = np.random.default_rng(int(kappa * 10))
+    idx = rng.integers(0, n, size=20000).astype(np.uint64)
+    if precision == kp.FP32:
+        idx = np.concatenate([idx, orc.find_tails(n, c["seed"])])
+    idx = np.concatenate([idx, np.array([0, 1, n - 2, n - 1], dtype=np.uint64)])
+    it = torch.from_numpy(idx.astype(np.int64)).cuda()
+    g = to_host(*(t[it] for t in v))
+    r = orc.sample_indices(kappa, c["theta"], idx, c["seed"], mode=MODE[precision])
+    err = norm_rel_err(g, r)
+    print(f"C2 kappa {kappa} precision {precision}: {idx.size} particles, max error {err:.3e}")
+    assert err <= (TOL_FP64 if precision == kp.FP64 else TOL_FP32)
+    assert all(bool(torch.isfinite(t).all()) for t in v)
+
+
+def test_determinism_and_chunking():
+    n = 3_000_001
+    for precision in (kp.FP64, kp.FP32):
+        a = to_host(*gpu_sample(2.0, 1.0, n, 7, precision))
+        b = to_host(*gpu_sample(2.0, 1.0, n, 7, precision))
+        assert bits_equal(a, b)
+        cut = 1_234_567
+        c1 = to_host(*gpu_sample(2.0, 1.0, cut, 7, precision))
+        c2 = to_host(*gpu_sample(2.0, 1.0, n - cut, 7, precision, counter_offset=cut))
+        assert bits_equal(a, tuple(np.concatenate([x, y]) for x, y in zip(c1, c2)))
+
+
+def test_store_path_invariance():
+    """Misaligned outputs take the one-particle-per-thread path; results are
+    bit-identical to the 16-byte vector-store path."""
+    n = 100_000
+    for precision in (kp.FP64, kp.FP32):
+        dt = torch.float64 if precision == kp.FP64 else torch.float32
+        base = [torch.empty(n + 1, dtype=dt, device="cuda") for _ in range(3)]
+        mis = tuple(t[1:] for t in base)
+        assert all(t.data_ptr() % 16 != 0 for t in mis)
+        kp.sample(4.0, 1.0, n, 3, precision=precision, out=mis)
+        ref = kp.sample(4.0, 1.0, n, 3, precision=precision)
+        torch.cuda.synchronize()
+        assert bits_equal(to_host(*mis), to_host(*ref))
+
+
+def test_seg_id_selects_independent_stream(orc):
+    n = 10_000
+    a = to_host(*gpu_sample(3.0, 1.0, n, 1, kp.FP64, seg_id=5))
+    r = orc.sample(3.0, 1.0, n, 1, seg=5, mode=0)[:3]
+    assert norm_rel_err(a, r) <= TOL_FP64
+    b = to_host(*gpu_sample(3.0, 1.0, n, 1, kp.FP64, seg_id=6))
+    assert not np.allclose(a[0], b[0])
+
+
+def test_device_errors_are_reported():
+    """A 1-byte misaligned float pointer is rejected with KAPPA_EALIGN."""
+    buf = torch.empty(64, dtype=torch.uint8, device="cuda")
+    import ctypes
+    from paper_2602_05606_amd import _lib
+    p = ctypes.c_void_p(buf.data_ptr() + 1)
+    st = _lib.load().kappa_sample(3.0, 1.0, 4, 0, 0, 0, kp.FP32, p, p, p, None)
+    assert st == _lib.EALIGN
