@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run the plain copy probe on 1.2e9 bytes (3 launches) and the store probe, so that "
+                         "rocprofv3 counters can be scaled against known traffic")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the generator needs no communication, and a run on N GPUs is "
@@ -157,6 +160,18 @@ def main():
                      "kernel": "forward_kernel<FP32 tail, 4 particles/thread>",
                      "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
     }
+
+    if args.calibrate:
+        src = torch.empty(300_000_000, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            kp.copy_probe(src, dst)
+        for _ in range(3):
+            kp.fill_probe(n, kp.FP32, out32)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copies done (copy_kernel: 1.2e9 bytes read and written per launch; "
+            "fill_kernel: 1.2e9 bytes written per launch)")
 
     if not args.no_extras:
         extras = {}

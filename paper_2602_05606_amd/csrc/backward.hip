@@ -65,6 +65,22 @@ __device__ __forceinline__ double dk_term_f64(const InvF64 &inv, const SpeciesF6
     return vg * (-num / inv.D) / (2.0 * x);
 }
 
+// dL/dkappa at fixed U1 in FP32: z e^z - expm1(z).  For z < 1/2 the two terms
+// cancel to z^2/2, so the series z^2 sum_{n>=2} (n-1)/n! z^(n-2) is used
+// (truncated after n = 9, relative error < 2e-8 at z = 1/2).
+__device__ __forceinline__ float dL_dkappa_f32(const InvF32 &inv)
+{
+    const float z = inv.z;
+    float p = fmaf(1.0f / 45360.0f, z, 1.0f / 5760.0f);
+    p = fmaf(p, z, 1.0f / 840.0f);
+    p = fmaf(p, z, 1.0f / 144.0f);
+    p = fmaf(p, z, 1.0f / 30.0f);
+    p = fmaf(p, z, 1.0f / 8.0f);
+    p = fmaf(p, z, 1.0f / 3.0f);
+    p = fmaf(p, z, 0.5f);
+    return z < 0.5f ? z * z * p : fmaf(z, inv.ez, -inv.em1);
+}
+
 template <int MODE, int U, bool VEC>
 __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
 {
@@ -109,22 +125,21 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                 acc_k += dk_term_f64(inv, a.s64, vg);
             } else {
                 bool high;
-                float u;
-                speed_uniform_f32(b.r0, high, u);
-                const InvF32 inv = invert_f32(high, u, a.s32);
+                float y1, d1;
+                speed_uniform_f32(b.r0, high, y1, d1);
+                const InvF32 inv = invert_f32(high, y1, d1, a.s32);
                 const DirF32 d = direction_f32(b.r1, b.r2);
                 const float dot = d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k];
                 if (MODE == kModeF32 && __builtin_expect(in_fp64_tail(b.r0), 0)) {
                     tail_dot[k] = dot;
                     tails |= 1u << k;
                 } else {
-                    const float V = a.s32.theta * sqrtf(inv.x);
+                    const float V = a.s32.theta * __builtin_amdgcn_sqrtf(inv.x);
                     const float vg = V * dot;
-                    const float ez = expf(inv.z);
-                    const float dL = -expm1f(inv.z) + inv.z * ez;
+                    const float dL = dL_dkappa_f32(inv);
                     const float x = inv.x;
                     const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
-                    const float term = vg * (-num / inv.D) / (2.0f * x);
+                    const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
                     acc_s += static_cast<double>(vg);
                     acc_k += static_cast<double>(term);
                 }

@@ -32,8 +32,8 @@ namespace {
 constexpr uint64_t kTile = 1024;  // particles per tile of the segment map
 
 struct alignas(16) SegF32 {
-    float kstar, inv_kstar, a, b, c, half_inv_b, theta, dx, dy, dz;
-    uint32_t seg_id, pad;
+    float kstar, inv_kstar, ln2_inv_kstar, a, c, two_b, four_b, theta, dx, dy, dz;
+    uint32_t seg_id;
 };
 
 struct alignas(16) SegF64 {
@@ -120,7 +120,15 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 z[k] += q.dz;
             } else {
                 const SegF32 q = a.seg32[s];
-                SpeciesF32 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.half_inv_b, q.theta, 0, 0, 0};
+                SpeciesF32 sp{};
+                sp.kstar = q.kstar;
+                sp.inv_kstar = q.inv_kstar;
+                sp.ln2_inv_kstar = q.ln2_inv_kstar;
+                sp.a = q.a;
+                sp.c = q.c;
+                sp.two_b = q.two_b;
+                sp.four_b = q.four_b;
+                sp.theta = q.theta;
                 particle_f32(b, sp, x[k], y[k], z[k]);
                 x[k] += q.dx;
                 y[k] += q.dy;
@@ -367,9 +375,9 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
         const SpeciesF32 b = species_f32(it->second, segs[s].theta);
         s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.half_inv_b, a.theta,
                         segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
-        s32[s] = SegF32{b.kstar, b.inv_kstar, b.a, b.b, b.c, b.half_inv_b, b.theta,
+        s32[s] = SegF32{b.kstar, b.inv_kstar, b.ln2_inv_kstar, b.a, b.c, b.two_b, b.four_b, b.theta,
                         static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),
-                        static_cast<float>(segs[s].drift[2]), segs[s].seg_id, 0};
+                        static_cast<float>(segs[s].drift[2]), segs[s].seg_id};
         ids[s] = segs[s].seg_id;
     }
     start[nseg] = acc;

@@ -5,6 +5,9 @@
 // The forward pass is a pure streaming write: 3 x sizeof(T) bytes per particle
 // and no reads.  Each thread produces `U` consecutive particles entirely in
 // registers and writes them with one 16-byte store per output array.
+#include <cstdio>
+#include <cstdlib>
+
 #include "kappa_device.hpp"
 #include "kappa_internal.hpp"
 
@@ -103,14 +106,31 @@ hipError_t launch_mode(const Shape &sh, const FwdArgs &a, hipStream_t stream)
 
 }  // namespace
 
+// One thread per group of particles (the grid-stride loop runs once) up to
+// 2^30 blocks: consecutive workgroups then write consecutive address ranges,
+// which measured faster for streaming stores on gfx950 than a grid capped at
+// a few workgroups per CU striding over the arrays.
+// The environment variable KAPPA_FORWARD_SHAPE="block,unroll,blocks_per_cu"
+// overrides the shape for tuning (block in {64,128,256}, unroll in {1,2,4,8},
+// blocks_per_cu 0 for one thread per group).  Results never depend on it.
 Shape forward_shape(int mode, uint64_t n, bool vec)
 {
     Shape s;
     s.block = 256;
     s.unroll = vec ? (mode == kModeF64 ? 2 : 4) : 1;
+    uint64_t per_cu = 0;
+    if (const char *env = std::getenv("KAPPA_FORWARD_SHAPE")) {
+        int b = 0, u = 0, w = -1;
+        if (std::sscanf(env, "%d,%d,%d", &b, &u, &w) == 3 && (b == 64 || b == 128 || b == 256) &&
+            (u == 1 || u == 2 || u == 4 || u == 8) && w >= 0) {
+            s.block = b;
+            s.unroll = vec ? u : 1;
+            per_cu = static_cast<uint64_t>(w);
+        }
+    }
     const uint64_t groups = (n + s.unroll - 1) / s.unroll;
     const uint64_t need = (groups + s.block - 1) / s.block;
-    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 16;
+    const uint64_t cap = per_cu ? per_cu * static_cast<uint64_t>(device_cu_count()) : (1ull << 30);
     s.grid = static_cast<int>(need < cap ? (need > 0 ? need : 1) : cap);
     return s;
 }

@@ -21,6 +21,12 @@ struct Block4 {
     uint32_t r0, r1, r2, r3;
 };
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96 is the three-input XOR).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
 {
@@ -30,8 +36,8 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
         const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
         c1 = static_cast<uint32_t>(pb);
         c3 = static_cast<uint32_t>(pa);
         c0 = n0;
@@ -95,27 +101,53 @@ __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF
     return r;
 }
 
+// FP32 path.  It runs on the hardware base-2 transcendentals (v_log_f32,
+// v_exp_f32), v_sqrt_f32 and v_rcp_f32, each within 2 ulp, and expm1 of
+// arguments in [-1/2, 1/2] by a degree-6 polynomial for expm1(x)/x
+// (near-minimax, Chebyshev nodes; 4e-9 approximation error, 8e-8 in FP32
+// evaluation).  Same evaluation order as invert_f64, in base 2.
+__device__ __forceinline__ float expm1_poly(float x)
+{
+    float p = fmaf(0x1.a2a31ep-13f, x, 0x1.6ef178p-10f);
+    p = fmaf(p, x, 0x1.110fccp-7f);
+    p = fmaf(p, x, 0x1.55527ap-5f);
+    p = fmaf(p, x, 0x1.555556p-3f);
+    p = fmaf(p, x, 0x1.000002p-1f);
+    p = fmaf(p, x, 1.0f);
+    return x * p;
+}
+
 struct InvF32 {
-    float z, L, D, x;
+    float z;    // -lT / kappa*
+    float ez;   // e^z
+    float em1;  // e^z - 1
+    float L, D, x;
 };
 
-__device__ __forceinline__ InvF32 invert_f32(bool high, float u, const SpeciesF32 &s)
+__device__ __forceinline__ InvF32 invert_f32(bool high, float y1, float d1, const SpeciesF32 &s)
 {
-    const float y1 = high ? 1.0f - u : u;
-    const float d1 = high ? (1.0f - y1) - u : 0.0f;
-    const float l1 = logf(y1) + d1 / y1;
-    const float p = (2.0f / 3.0f) * l1;
-    const float t = expf(p);
-    const float em1 = expm1f(p);
-    const float y2 = high ? -em1 : 1.0f - t;
-    const float d2 = high ? 0.0f : (1.0f - y2) - t;
-    const float lT = logf(y2) + d2 / y2;
+    constexpr float kLog2e = 0x1.715476p+0f, kLn2 = 0x1.62e430p-1f;
+    // log2 U1 = log2(y1 + d1): one hardware log for both sides; the residual
+    // (|d1| <= 2^-25, y1 >= 1/2 where it is non-zero) enters as d1 log2(e),
+    // whose missing 1/y1 factor changes log2 U1 by less than 2^-24 relative.
+    const float l1 = fmaf(d1, kLog2e, __builtin_amdgcn_logf(y1));
+    const float p2 = l1 * (2.0f / 3.0f);               // log2 U1^{2/3}
+    const float e = __builtin_amdgcn_exp2f(p2);         // U1^{2/3} (low side)
+    const float em1q = expm1_poly(p2 * kLn2);           // U1^{2/3} - 1 (high side, |arg| <= 0.47)
+    const float y2 = high ? -em1q : 1.0f - e;
+    const float d2 = high ? 0.0f : (1.0f - y2) - e;
+    const float lT2 = fmaf(d2, kLog2e, __builtin_amdgcn_logf(y2));  // log2(1 - U1^{2/3})
     InvF32 r;
-    r.z = -lT * s.inv_kstar;
-    r.L = -s.kstar * expm1f(r.z);
+    r.z = -lT2 * s.ln2_inv_kstar;
+    r.ez = __builtin_amdgcn_exp2f(-lT2 * s.inv_kstar);
+    r.em1 = (r.z < 0.5f) ? expm1_poly(r.z) : r.ez - 1.0f;
+    r.L = -s.kstar * r.em1;
     const float A = fmaf(s.c, r.L, s.a);
-    r.D = sqrtf(fmaf(A, A, -4.0f * s.b * r.L));
-    r.x = (A >= 0.0f) ? (-2.0f * r.L) / (A + r.D) : (r.D - A) * s.half_inv_b;
+    r.D = __builtin_amdgcn_sqrtf(fmaf(A, A, -s.four_b * r.L));
+    const bool pos = A >= 0.0f;
+    const float num = pos ? -2.0f * r.L : r.D - A;
+    const float den = pos ? A + r.D : s.two_b;
+    r.x = num * __builtin_amdgcn_rcpf(den);
     return r;
 }
 
@@ -135,12 +167,17 @@ __device__ __forceinline__ void speed_uniform_f64(uint32_t r0, uint32_t r3, bool
 }
 
 // FP32 bulk: m24 = r0 >> 8.  Tail when m24 >= 2^24 - 16 (1 - U1 < 2^-20).
-__device__ __forceinline__ void speed_uniform_f32(uint32_t r0, bool &high, float &u)
+// On both sides U1 = k 2^-25 with k = 2 m24 + 1 < 2^25.  y1 = fl(U1) and the
+// residual d1 = U1 - y1 (0 on the low side, where k < 2^24 is exact; +-2^-25
+// on the high side) are formed exactly from the integer, so 1 - U1 never
+// needs to be represented: ln U1 = ln(y1 + d1).
+__device__ __forceinline__ void speed_uniform_f32(uint32_t r0, bool &high, float &y1, float &d1)
 {
-    const uint32_t m = r0 >> 8;
-    high = m >= (1u << 23);
-    const uint32_t k = high ? (1u << 25) - 2 * m - 1 : 2 * m + 1;  // < 2^24: exact in float
-    u = static_cast<float>(k) * 0x1p-25f;
+    const uint32_t k = (r0 >> 7) | 1u;  // 2 m24 + 1
+    high = r0 >= 0x80000000u;           // m24 >= 2^23
+    const float kf = static_cast<float>(k);
+    y1 = kf * 0x1p-25f;
+    d1 = static_cast<float>(static_cast<int32_t>(k - static_cast<uint32_t>(kf))) * 0x1p-25f;
 }
 
 __device__ __forceinline__ bool in_fp64_tail(uint32_t r0)
@@ -172,18 +209,19 @@ struct DirF32 {
     float cx, cy, cz;
 };
 
+// v_sin_f32 / v_cos_f32 take their argument in revolutions, so sin(2 pi U3)
+// needs no range reduction (absolute error 1.3e-7 on gfx950).  U3 is rounded
+// to float (error <= 2^-26) on its way in.
 __device__ __forceinline__ DirF32 direction_f32(uint32_t r1, uint32_t r2)
 {
-    const int32_t k = static_cast<int32_t>(2 * (r1 >> 8) + 1) - (1 << 24);  // |k| < 2^24
+    const int32_t k = static_cast<int32_t>((r1 >> 7) | 1u) - (1 << 24);  // |k| < 2^24
     const float ct = static_cast<float>(k) * 0x1p-24f;
-    const float st = sqrtf((1.0f - ct) * (1.0f + ct));
-    const float u3x2 = static_cast<float>(2 * (r2 >> 8) + 1) * 0x1p-24f;  // 2 U3
-    float sp, cp;
-    sincospif(u3x2, &sp, &cp);
+    const float st = __builtin_amdgcn_sqrtf((1.0f - ct) * (1.0f + ct));
+    const float u3 = static_cast<float>((r2 >> 7) | 1u) * 0x1p-25f;      // (m + 1/2) 2^-24
     DirF32 d;
     d.cx = ct;
-    d.cy = st * cp;
-    d.cz = st * sp;
+    d.cy = st * __builtin_amdgcn_cosf(u3);
+    d.cz = st * __builtin_amdgcn_sinf(u3);
     return d;
 }
 
@@ -209,10 +247,10 @@ __device__ __forceinline__ void particle_f64(const Block4 &b, const SpeciesF64 &
 __device__ __forceinline__ void particle_f32(const Block4 &b, const SpeciesF32 &s, float &vx, float &vy, float &vz)
 {
     bool high;
-    float u;
-    speed_uniform_f32(b.r0, high, u);
-    const InvF32 inv = invert_f32(high, u, s);
-    const float V = s.theta * sqrtf(inv.x);
+    float y1, d1;
+    speed_uniform_f32(b.r0, high, y1, d1);
+    const InvF32 inv = invert_f32(high, y1, d1, s);
+    const float V = s.theta * __builtin_amdgcn_sqrtf(inv.x);
     const DirF32 d = direction_f32(b.r1, b.r2);
     vx = V * d.cx;
     vy = V * d.cy;
