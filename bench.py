@@ -67,6 +67,48 @@ def time_launches(fn, reps, torch):
     return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / reps
 
 
+def exact_cdf_table(kappa, points=1 << 20):
+    """The exact Kappa speed CDF (eq:CDF) tabulated in y = x / (x + kappa) on
+    [0, 1], for interpolation on the GPU (scipy's regularized incomplete beta)."""
+    import numpy as np
+    from scipy import special
+    y = np.linspace(0.0, 1.0, points + 1)
+    return special.betainc(1.5, kappa - 0.5, y)
+
+
+def ks_distance(torch, vx, vy, vz, theta, kappa, table):
+    """Kolmogorov-Smirnov distance of the speeds against the exact CDF, on the GPU."""
+    x = ((vx.double() ** 2 + vy.double() ** 2 + vz.double() ** 2) / theta ** 2)
+    x, _ = torch.sort(x)
+    y = x / (x + kappa)
+    tab = torch.as_tensor(table, device=x.device)
+    pos = y * (tab.numel() - 1)
+    i0 = torch.clamp(pos.floor().long(), 0, tab.numel() - 2)
+    w = pos - i0.double()
+    f = tab[i0] * (1 - w) + tab[i0 + 1] * w
+    n = x.numel()
+    hi = torch.arange(1, n + 1, device=x.device, dtype=torch.float64) / n
+    return float(torch.maximum((hi - f).max(), (f - (hi - 1.0 / n)).max()))
+
+
+def ks_table(kp, torch, kappas, theta, seed, out32, n_ks=10 ** 7):
+    """KS distance against the exact CDF at n_ks particles for the approximate
+    generator and the two exact ones, with the 1.36/sqrt(n) 5% critical value."""
+    res = {"n": n_ks, "critical_5pct": 1.36 / n_ks ** 0.5}
+    sub = tuple(t[:n_ks] for t in out32)
+    for k in kappas:
+        table = exact_cdf_table(k)
+        row = {}
+        kp.sample(k, theta, n_ks, seed, precision=kp.FP32, out=sub)
+        row["approx"] = ks_distance(torch, *sub, theta, k, table)
+        kp.sample_exact_t(k, theta, n_ks, seed, precision=kp.FP32, out=sub)
+        row["t_gamma"] = ks_distance(torch, *sub, theta, k, table)
+        kp.sample_exact_pareto(k, theta, n_ks, seed, precision=kp.FP32, out=sub)
+        row["pareto"] = ks_distance(torch, *sub, theta, k, table)
+        res[str(k)] = row
+    return res
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (FP64 arithmetic at the FP32 mode's uniforms, OpenMP over
     particles) timed on the host over a bounded sample of the C2 workload."""
@@ -196,6 +238,22 @@ def main():
                              "approx_speedup_vs_pareto": per_kappa[str(k)] / rate_p}
         extras["exact_generators_fp32_particles_per_s"] = exact
         log("exact generators done")
+        extras["ks_vs_exact_cdf"] = ks_table(kp, torch, kappas, theta, seed, out32)
+        log("KS distances done")
+        c5 = workloads.C5
+        chunk_out = tuple(t[:c5["chunk"]] for t in out32) if c5["chunk"] <= n else None
+        if chunk_out is None:
+            chunk_out = tuple(torch.empty(c5["chunk"], dtype=torch.float32, device=dev) for _ in range(3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for off, cnt in workloads.c5_chunks():
+            kp.sample(c5["kappa"], c5["theta"], cnt, c5["seed"], counter_offset=off, precision=kp.FP32,
+                      out=tuple(t[:cnt] for t in chunk_out))
+        torch.cuda.synchronize()
+        dt5 = time.perf_counter() - t0
+        extras["c5_stream_fp32"] = {"particles": c5["n"], "chunks": len(workloads.c5_chunks()), "s": dt5,
+                                    "particles_per_s": c5["n"] / dt5}
+        del chunk_out
         del out32
         out64 = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
         fp64 = {}

@@ -134,10 +134,10 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                     tail_dot[k] = dot;
                     tails |= 1u << k;
                 } else {
-                    const float V = a.s32.theta * __builtin_amdgcn_sqrtf(inv.x);
+                    const float x = inv.x();
+                    const float V = a.s32.theta * __builtin_amdgcn_sqrtf(x);
                     const float vg = V * dot;
                     const float dL = dL_dkappa_f32(inv);
-                    const float x = inv.x;
                     const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
                     const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
                     acc_s += static_cast<double>(vg);

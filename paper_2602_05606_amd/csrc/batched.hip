@@ -301,6 +301,9 @@ BatchArgs batch_args(const kappa_plan_s *p, void *vx, void *vy, void *vz)
     return a;
 }
 
+// One thread per group of particles: the whole plan in one pass of
+// workgroups, with no partly filled second pass (a grid of a few workgroups
+// per CU striding over 5e6 particles leaves one).
 Shape default_batched_shape(int mode, uint64_t total)
 {
     Shape s;
@@ -308,8 +311,7 @@ Shape default_batched_shape(int mode, uint64_t total)
     s.unroll = mode == kModeF64 ? 2 : 4;
     const uint64_t groups = (total + s.unroll - 1) / s.unroll;
     const uint64_t need = (groups + s.block - 1) / s.block;
-    const uint64_t cap = static_cast<uint64_t>(device_cu_count()) * 8;
-    s.grid = static_cast<int>(std::max<uint64_t>(1, std::min(need, cap)));
+    s.grid = static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(need, 1ull << 30)));
     return s;
 }
 
@@ -512,16 +514,16 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
     const int cus = device_cu_count();
     const int blocks[] = {64, 128, 256};
     const int unrolls[] = {1, 2, 4, 8};
-    const int per_cu[] = {1, 2, 4, 8, 16};
+    const int per_cu[] = {0, 1, 2, 4, 8, 16};  // 0: one thread per group
     float best_ms = 1e30f;
     Shape best = p->shape;
     for (int b : blocks)
         for (int u : unrolls)
             for (int w : per_cu) {
-                Shape cand{b, u, w * cus};
                 const uint64_t groups = (p->total + u - 1) / u;
                 const uint64_t need = (groups + b - 1) / b;
-                if (static_cast<uint64_t>(cand.grid) > need && w > 1) continue;  // more blocks than work
+                Shape cand{b, u, w > 0 ? w * cus : static_cast<int>(std::min<uint64_t>(need, 1ull << 30))};
+                if (w > 0 && static_cast<uint64_t>(cand.grid) >= need) continue;  // same as one pass
                 if (!aligned_for(p->mode, cand, vx, vy, vz)) continue;
                 const BatchArgs a = batch_args(p, vx, vy, vz);
                 hipError_t err = launch_batched(p->mode, cand, a, st);  // warm-up

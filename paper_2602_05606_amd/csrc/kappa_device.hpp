@@ -118,10 +118,14 @@ __device__ __forceinline__ float expm1_poly(float x)
 }
 
 struct InvF32 {
-    float z;    // -lT / kappa*
-    float ez;   // e^z
-    float em1;  // e^z - 1
-    float L, D, x;
+    float z;         // -lT / kappa*
+    float ez;        // e^z
+    float em1;       // e^z - 1
+    float L, D;
+    float num, den;  // x = (V/theta)^2 = num / den, both > 0
+    __device__ __forceinline__ float x() const { return num * __builtin_amdgcn_rcpf(den); }
+    // sqrt(x) = num / sqrt(num den): one transcendental instead of rcp and sqrt
+    __device__ __forceinline__ float sqrt_x() const { return num * __builtin_amdgcn_rsqf(num * den); }
 };
 
 __device__ __forceinline__ InvF32 invert_f32(bool high, float y1, float d1, const SpeciesF32 &s)
@@ -145,9 +149,8 @@ __device__ __forceinline__ InvF32 invert_f32(bool high, float y1, float d1, cons
     const float A = fmaf(s.c, r.L, s.a);
     r.D = __builtin_amdgcn_sqrtf(fmaf(A, A, -s.four_b * r.L));
     const bool pos = A >= 0.0f;
-    const float num = pos ? -2.0f * r.L : r.D - A;
-    const float den = pos ? A + r.D : s.two_b;
-    r.x = num * __builtin_amdgcn_rcpf(den);
+    r.num = pos ? -2.0f * r.L : r.D - A;
+    r.den = pos ? A + r.D : s.two_b;
     return r;
 }
 
@@ -250,7 +253,7 @@ __device__ __forceinline__ void particle_f32(const Block4 &b, const SpeciesF32 &
     float y1, d1;
     speed_uniform_f32(b.r0, high, y1, d1);
     const InvF32 inv = invert_f32(high, y1, d1, s);
-    const float V = s.theta * __builtin_amdgcn_sqrtf(inv.x);
+    const float V = s.theta * inv.sqrt_x();
     const DirF32 d = direction_f32(b.r1, b.r2);
     vx = V * d.cx;
     vy = V * d.cy;
