@@ -23,7 +23,7 @@
  *            seg, precision): never on grid, block, unroll, stream or device,
  *            and a range can be produced in chunks by advancing counter_offset.
  *   uniforms U1 from the Philox words (r0, r3), U2 from r1, U3 from r2, as
- *            open midpoint dyadics (see KAPPA_FP64 / KAPPA_FP32 below).
+ *            open midpoint dyadics (see KAPPA_FP64 below), in every precision.
  *   outputs  structure-of-arrays vx[n], vy[n], vz[n], device pointers owned by
  *            the caller, written and never read.  double for KAPPA_FP64,
  *            float for KAPPA_FP32 and KAPPA_FP32_NOTAIL.  Each pointer must be
@@ -67,10 +67,10 @@ typedef enum {
      * if m < 2^52, else 1 - U1 = (2^54 - 2m - 1) 2^-54; U2 = (r1 + 1/2) 2^-32,
      * U3 = (r2 + 1/2) 2^-32.  double outputs. */
     KAPPA_FP64 = 0,
-    /* FP32 bulk with an FP64 tail.  U1 from m24 = r0 >> 8 by the same map with
-     * 24 bits, U2, U3 from the top 24 bits of r1, r2.  When 1 - U1 < 2^-20
-     * (m24 >= 2^24 - 16, probability 2^-20) the inversion is redone in FP64
-     * with the 53-bit U1 of KAPPA_FP64 and the speed rounded to float.
+    /* FP32 bulk with an FP64 tail.  The same uniforms as KAPPA_FP64 (each
+     * rounded to float inside the FP32 arithmetic), so the two precisions
+     * differ only in arithmetic.  When 1 - U1 < 2^-20 (r0 >= 0xFFFFF000,
+     * probability 2^-20) the speed is inverted in FP64 and rounded to float.
      * float outputs. */
     KAPPA_FP32 = 1,
     /* KAPPA_FP32 without the FP64 tail (diagnostics only). float outputs. */

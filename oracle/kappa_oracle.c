@@ -150,71 +150,45 @@ void oracle_params(double kappa, double *p)
 /* Uniform maps.  The paper draws U1, U2, U3 ~ Uniform(0,1) (Table 1) and
  * warns against a zero uniform (Sec. 6).  Reading used here: open midpoint
  * dyadics, with U1 carried as (side, small value) so that both U1 and 1-U1
- * are exact.
- *   mode 0 (FP64): m = top 53 bits of (r0:r3).  m < 2^52: U1 = (2m+1) 2^-54
- *                  on the low side; else W1 = 1 - U1 = (2^54-2m-1) 2^-54.
- *                  U2 = (r1 + 1/2) 2^-32, U3 = (r2 + 1/2) 2^-32.
- *   mode 1 (FP32 bulk, FP64 tail): m24 = r0 >> 8, same map with 24 bits;
- *                  if m24 >= 2^24 - 16 (W1 < 2^-20) the FP64 W1 of mode 0
- *                  is used instead.  U2, U3 from the top 24 bits of r1, r2.
- *   mode 2: mode 1 without the tail refinement (diagnostics).              */
+ * are exact, and the same uniforms in every precision mode:
+ *   m = top 53 bits of (r0:r3).  m < 2^52: U1 = (2m+1) 2^-54 on the low
+ *   side; else W1 = 1 - U1 = (2^54-2m-1) 2^-54.  U2 = (r1 + 1/2) 2^-32,
+ *   U3 = (r2 + 1/2) 2^-32.
+ * The modes differ only in the arithmetic the GPU uses (the oracle always
+ * computes in FP64): mode 0 FP64; mode 1 FP32 with an FP64 inversion when
+ * W1 < 2^-20 (r0 >= 0xFFFFF000, probability exactly 2^-20), reported as
+ * "tail"; mode 2 FP32 throughout (diagnostics).                            */
 /* ------------------------------------------------------------------------ */
 
 enum { SIDE_LOW = 0, SIDE_HIGH = 1 };
 enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_NOTAIL = 2 };
 
-/* Returns 1 when the FP64 tail refinement was taken. */
+/* Returns 1 when mode 1 takes the FP64 tail inversion for this particle. */
 int oracle_speed_uniform(int mode, uint32_t r0, uint32_t r3, int *side, double *u)
 {
     uint64_t m53 = ((((uint64_t)r0) << 32) | (uint64_t)r3) >> 11;
-    uint32_t m24 = r0 >> 8;
-    int use53 = (mode == MODE_FP64);
-    int tail = 0;
-    if (mode != MODE_FP64 && m24 >= (1u << 24) - 16u) {
-        tail = (mode == MODE_FP32);
-        use53 = tail;
-    }
-    if (use53) {
-        if (m53 < (1ull << 52)) {
-            *side = SIDE_LOW;
-            *u = ldexp((double)(2 * m53 + 1), -54);
-        } else {
-            *side = SIDE_HIGH;
-            *u = ldexp((double)((1ull << 54) - 2 * m53 - 1), -54);
-        }
+    if (m53 < (1ull << 52)) {
+        *side = SIDE_LOW;
+        *u = ldexp((double)(2 * m53 + 1), -54);
     } else {
-        if (m24 < (1u << 23)) {
-            *side = SIDE_LOW;
-            *u = ldexp((double)(2 * m24 + 1), -25);
-        } else {
-            *side = SIDE_HIGH;
-            *u = ldexp((double)((1u << 25) - 2 * m24 - 1), -25);
-        }
+        *side = SIDE_HIGH;
+        *u = ldexp((double)((1ull << 54) - 2 * m53 - 1), -54);
     }
-    return tail;
+    return mode == MODE_FP32 && r0 >= 0xFFFFF000u;
 }
 
 /* cos(theta) = 2 U2 - 1 and U2 (1 - U2), both from the integer word. */
-static void polar_uniform(int mode, uint32_t r1, double *cos_t, double *u2_1mu2)
+static void polar_uniform(uint32_t r1, double *cos_t, double *u2_1mu2)
 {
-    if (mode == MODE_FP64) {
-        double lo = (double)r1 + 0.5;             /* U2 * 2^32 */
-        double hi = 4294967296.0 - (double)r1 - 0.5; /* (1 - U2) * 2^32 */
-        *cos_t = ldexp((double)(2 * (int64_t)r1 + 1 - 4294967296LL), -32);
-        *u2_1mu2 = ldexp(lo * hi, -64);
-    } else {
-        uint32_t m = r1 >> 8;
-        double lo = (double)m + 0.5, hi = 16777216.0 - (double)m - 0.5;
-        *cos_t = ldexp((double)(2 * (int64_t)m + 1 - 16777216LL), -24);
-        *u2_1mu2 = ldexp(lo * hi, -48);
-    }
+    double lo = (double)r1 + 0.5;                /* U2 * 2^32 */
+    double hi = 4294967296.0 - (double)r1 - 0.5; /* (1 - U2) * 2^32 */
+    *cos_t = ldexp((double)(2 * (int64_t)r1 + 1 - 4294967296LL), -32);
+    *u2_1mu2 = ldexp(lo * hi, -64);
 }
 
-static double azimuth_uniform(int mode, uint32_t r2)
+static double azimuth_uniform(uint32_t r2)
 {
-    if (mode == MODE_FP64)
-        return ldexp((double)r2 + 0.5, -32);
-    return ldexp((double)(r2 >> 8) + 0.5, -24);
+    return ldexp((double)r2 + 0.5, -32);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -307,9 +281,9 @@ static int one_particle(const double *p, double theta, const double *drift, int 
     invert(p, side, u, &inv);
     double V = theta * sqrt(inv.x);
     double cos_t, u2prod;
-    polar_uniform(mode, r[1], &cos_t, &u2prod);
+    polar_uniform(r[1], &cos_t, &u2prod);
     double sin_t = 2.0 * sqrt(u2prod);
-    double phi = 2.0 * M_PI * azimuth_uniform(mode, r[2]);
+    double phi = 2.0 * M_PI * azimuth_uniform(r[2]);
     v[0] = V * cos_t + drift[0];
     v[1] = V * sin_t * cos(phi) + drift[1];
     v[2] = V * sin_t * sin(phi) + drift[2];
@@ -386,9 +360,9 @@ void oracle_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint
         invert(p, side, u, &inv);
         double V = theta * sqrt(inv.x);
         double cos_t, u2prod;
-        polar_uniform(mode, r[1], &cos_t, &u2prod);
+        polar_uniform(r[1], &cos_t, &u2prod);
         double sin_t = 2.0 * sqrt(u2prod);
-        double phi = 2.0 * M_PI * azimuth_uniform(mode, r[2]);
+        double phi = 2.0 * M_PI * azimuth_uniform(r[2]);
         double v0 = V * cos_t, v1 = V * sin_t * cos(phi), v2 = V * sin_t * sin(phi);
         double s = (double)gx[j] * v0 + (double)gy[j] * v1 + (double)gz[j] * v2;
         double dL = -expm1(inv.z) + inv.z * exp(inv.z);
@@ -401,9 +375,9 @@ void oracle_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint
     out[1] = sum_t;
 }
 
-/* Indices j in [counter_offset, counter_offset + n) whose FP32-mode U1 takes
- * the FP64 tail (1 - U1 < 2^-20), in increasing order; at most max_out are
- * written.  Returns how many there are. */
+/* Indices j in [counter_offset, counter_offset + n) for which the FP32 mode
+ * takes the FP64 tail inversion (1 - U1 < 2^-20), in increasing order; at
+ * most max_out are written.  Returns how many there are. */
 uint64_t oracle_find_tails(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg, uint64_t *out,
                            uint64_t max_out)
 {
@@ -421,7 +395,7 @@ uint64_t oracle_find_tails(uint64_t n, uint64_t seed, uint64_t counter_offset, u
             for (uint64_t j = lo; j < hi; ++j) {
                 uint32_t r[4];
                 particle_block(seed, counter_offset + j, seg, 0, r);
-                if ((r[0] >> 8) >= (1u << 24) - 16u && counts[c - c0] < 16)
+                if (r[0] >= 0xFFFFF000u && counts[c - c0] < 16)
                     hits[c - c0][counts[c - c0]++] = counter_offset + j;
             }
         }

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
             } else {
                 bool high;
                 float y1, d1;
-                speed_uniform_f32(b.r0, high, y1, d1);
+                speed_uniform_f32(b.r0, b.r3, high, y1, d1);
                 const InvF32 inv = invert_f32(high, y1, d1, a.s32);
                 const DirF32 d = direction_f32(b.r1, b.r2);
                 const float dot = d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k];

@@ -170,17 +170,22 @@ __device__ __forceinline__ void speed_uniform_f64(uint32_t r0, uint32_t r3, bool
 }
 
 // FP32 bulk: m24 = r0 >> 8.  Tail when m24 >= 2^24 - 16 (1 - U1 < 2^-20).
-// On both sides U1 = k 2^-25 with k = 2 m24 + 1 < 2^25.  y1 = fl(U1) and the
-// residual d1 = U1 - y1 (0 on the low side, where k < 2^24 is exact; +-2^-25
-// on the high side) are formed exactly from the integer, so 1 - U1 never
-// needs to be represented: ln U1 = ln(y1 + d1).
-__device__ __forceinline__ void speed_uniform_f32(uint32_t r0, bool &high, float &y1, float &d1)
+// FP32 mode draws the FP64 mode's uniforms.  With R = (r0:r3) and its low 11
+// bits replaced by the midpoint bit 2^10, U1 = R 2^-64 exactly.  The small
+// side value s (U1 on the low side, 1 - U1 = (~r0, 2^32 - lo) 2^-64 on the
+// high side, taken from the integers without cancellation) is rounded to
+// float; then y1 = fl(U1) and the exact float residual d1 = (1 - y1) - s on
+// the high side give ln U1 = ln(y1 + d1) to float precision for any U1.
+__device__ __forceinline__ void speed_uniform_f32(uint32_t r0, uint32_t r3, bool &high, float &y1, float &d1)
 {
-    const uint32_t k = (r0 >> 7) | 1u;  // 2 m24 + 1
-    high = r0 >= 0x80000000u;           // m24 >= 2^23
-    const float kf = static_cast<float>(k);
-    y1 = kf * 0x1p-25f;
-    d1 = static_cast<float>(static_cast<int32_t>(k - static_cast<uint32_t>(kf))) * 0x1p-25f;
+    const uint32_t mask = static_cast<uint32_t>(static_cast<int32_t>(r0) >> 31);  // ones on the high side
+    high = mask != 0u;
+    const uint32_t lo = (r3 & 0xFFFFF800u) | 0x400u;
+    const uint32_t hw = r0 ^ mask;         // high side: ~r0
+    const uint32_t lw = (lo ^ mask) - mask;  // high side: 2^32 - lo
+    const float s = fmaf(static_cast<float>(lw), 0x1p-32f, static_cast<float>(hw)) * 0x1p-32f;
+    y1 = high ? 1.0f - s : s;
+    d1 = high ? (1.0f - y1) - s : 0.0f;
 }
 
 __device__ __forceinline__ bool in_fp64_tail(uint32_t r0)
@@ -213,16 +218,19 @@ struct DirF32 {
 };
 
 // v_sin_f32 / v_cos_f32 take their argument in revolutions, so sin(2 pi U3)
-// needs no range reduction (absolute error 1.3e-7 on gfx950).  U3 is rounded
-// to float (error <= 2^-26) on its way in.
+// needs no range reduction (absolute error 1.3e-7 on gfx950).  The uniforms
+// are the FP64 mode's: 1 + cos = 2 U2 = (r1 + 1/2) 2^-31 and
+// 1 - cos = 2 (1 - U2) = (~r1 + 1/2) 2^-31 each come from the integer word
+// without cancellation, so sin = sqrt((1 - cos)(1 + cos)) stays accurate at
+// the poles; U3 = (r2 + 1/2) 2^-32 is rounded to float (error <= 2^-24 U3).
 __device__ __forceinline__ DirF32 direction_f32(uint32_t r1, uint32_t r2)
 {
-    const int32_t k = static_cast<int32_t>((r1 >> 7) | 1u) - (1 << 24);  // |k| < 2^24
-    const float ct = static_cast<float>(k) * 0x1p-24f;
-    const float st = __builtin_amdgcn_sqrtf((1.0f - ct) * (1.0f + ct));
-    const float u3 = static_cast<float>((r2 >> 7) | 1u) * 0x1p-25f;      // (m + 1/2) 2^-24
+    const float opc = fmaf(static_cast<float>(r1), 0x1p-31f, 0x1p-32f);
+    const float omc = fmaf(static_cast<float>(~r1), 0x1p-31f, 0x1p-32f);
+    const float st = __builtin_amdgcn_sqrtf(opc * omc);
+    const float u3 = fmaf(static_cast<float>(r2), 0x1p-32f, 0x1p-33f);
     DirF32 d;
-    d.cx = ct;
+    d.cx = 0.5f * (opc - omc);
     d.cy = st * __builtin_amdgcn_cosf(u3);
     d.cz = st * __builtin_amdgcn_sinf(u3);
     return d;
@@ -251,7 +259,7 @@ __device__ __forceinline__ void particle_f32(const Block4 &b, const SpeciesF32 &
 {
     bool high;
     float y1, d1;
-    speed_uniform_f32(b.r0, high, y1, d1);
+    speed_uniform_f32(b.r0, b.r3, high, y1, d1);
     const InvF32 inv = invert_f32(high, y1, d1, s);
     const float V = s.theta * inv.sqrt_x();
     const DirF32 d = direction_f32(b.r1, b.r2);

@@ -55,7 +55,10 @@ def test_forward_parity_ragged(orc, kappa, precision):
     r = orc.sample(kappa, 1.7, n, 11, counter_offset=123, mode=MODE[precision])[:3]
     err = norm_rel_err(g, r)
     print(f"kappa {kappa} precision {precision}: max norm-relative error {err:.3e}")
-    assert err <= (TOL_FP64 if precision == kp.FP64 else TOL_FP32)
+    # FP32_NOTAIL (diagnostics) keeps FP32 arithmetic where 1 - U1 < 2^-20, where
+    # the error of z = -ln(1 - U1^{2/3})/kappa* is amplified by z (up to ~30)
+    tol = {kp.FP64: TOL_FP64, kp.FP32: TOL_FP32, kp.FP32_NOTAIL: 1e-5}[precision]
+    assert err <= tol
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 63, 64, 65, 1023, 4097])

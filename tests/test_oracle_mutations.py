@@ -26,7 +26,9 @@ MUTANTS = {
     "direction_swap": ("v[1] = V * sin_t * cos(phi)", "v[1] = V * sin_t * sin(phi)"),
     "philox_key_word": ("hi_b ^ x1 ^ k0", "hi_b ^ x1 ^ k1"),
     "philox_weyl": ("k1 += PHILOX_WEYL_B;", "k1 += PHILOX_WEYL_A;"),
-    "uniform_scale": ("*u = ldexp((double)(2 * m24 + 1), -25);", "*u = ldexp((double)(2 * m24 + 1), -24);"),
+    "uniform_scale": ("*u = ldexp((double)(2 * m53 + 1), -54);", "*u = ldexp((double)(2 * m53 + 1), -53);"),
+    "azimuth_word": ("double phi = 2.0 * M_PI * azimuth_uniform(r[2]);\n    v[0]", "double phi = 2.0 * M_PI * azimuth_uniform(r[1]);\n    v[0]"),
+    "tail_threshold": ("return mode == MODE_FP32 && r0 >= 0xFFFFF000u;", "return mode == MODE_FP32 && r0 >= 0xFFFFE000u;"),
     "fp64_word_order": ("((((uint64_t)r0) << 32) | (uint64_t)r3)", "((((uint64_t)r3) << 32) | (uint64_t)r0)"),
     "adjoint_L_term": ("(da + dc * L + c * dL)", "(da + dc * L + dc * dL)"),
     "adjoint_a_derivative": ("a * (-1.0 / kappa - (2.0 / 3.0) * dlnB)", "a * (-1.0 / kappa + (2.0 / 3.0) * dlnB)"),

@@ -4,8 +4,8 @@ Pins (none retypes the inversion):
   * round trip: the approximate CDF G of eq:G, coded separately in the oracle,
     evaluated at each sampled speed returns the uniform (eq:GU) to 1e-12,
     relative to U1 on the low side and to 1 - U1 on the high side;
-  * the uniform maps: exact midpoint dyadics, tail probability exactly 2^-20,
-    the tail refinement stays inside its 24-bit cell;
+  * the uniform map: exact midpoint dyadics shared by every mode, the FP32
+    mode's tail (1 - U1 < 2^-20) has probability exactly 2^-20;
   * |v| = V and isotropy of the direction (Table 1, last three rows);
   * KS of the speeds against the exact Kappa CDF (eq:CDF) at sizes where the
     approximation error is below the sampling noise, and against G itself;
@@ -88,34 +88,29 @@ def test_fp64_speed_uniform_map(orc):
         assert 0 < u <= 0.5
 
 
-def test_fp32_speed_uniform_map_and_tail(orc):
-    edge = [0, 1, (1 << 23) - 1, 1 << 23, (1 << 24) - 17, (1 << 24) - 16, (1 << 24) - 1]
+def test_fp32_modes_share_the_fp64_uniforms_and_flag_the_tail(orc):
+    """Every precision mode draws the same uniforms; the FP32 mode flags the
+    particles with 1 - U1 < 2^-20 (r0 >= 0xFFFFF000) for its FP64 inversion."""
     rng = np.random.default_rng(1)
-    cells = edge + rng.integers(0, 1 << 24, size=3000).tolist()
-    for m24 in cells:
-        for low8, r3 in ((0, 0), (255, 0xFFFFFFFF), (17, 12345)):
-            r0 = (m24 << 8) | low8
-            tail, side, u = orc.speed_uniform(orc.MODE_FP32, r0, r3)
-            assert tail == (m24 >= (1 << 24) - 16)
-            if not tail:
-                if m24 < (1 << 23):
-                    assert side == orc.SIDE_LOW and u == (2 * m24 + 1) * 2.0 ** -25
-                else:
-                    assert side == orc.SIDE_HIGH and u == ((1 << 25) - 2 * m24 - 1) * 2.0 ** -25
-            else:
-                # the 53-bit refinement lies inside the same 24-bit cell, whose W1 range
-                # is (2^24 - m24 - 1, 2^24 - m24] * 2^-24
-                assert side == orc.SIDE_HIGH
-                assert ((1 << 24) - m24 - 1) * 2.0 ** -24 < u <= ((1 << 24) - m24) * 2.0 ** -24
-                assert u < 2.0 ** -20
-                t2, s2, u2 = orc.speed_uniform(orc.MODE_FP32_NOTAIL, r0, r3)
-                assert not t2 and s2 == orc.SIDE_HIGH and u2 == ((1 << 25) - 2 * m24 - 1) * 2.0 ** -25
+    r0s = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFEFFF, 0xFFFFF000, 0xFFFFFFFF] + rng.integers(0, 1 << 32, 3000).tolist()
+    for r0 in r0s:
+        for r3 in (0, 0xFFFFFFFF, 12345):
+            ref = orc.speed_uniform(orc.MODE_FP64, r0, r3)
+            t32 = orc.speed_uniform(orc.MODE_FP32, r0, r3)
+            t2 = orc.speed_uniform(orc.MODE_FP32_NOTAIL, r0, r3)
+            assert t32[1:] == ref[1:] and t2[1:] == ref[1:]
+            assert not ref[0] and not t2[0]
+            assert t32[0] == (r0 >= 0xFFFFF000)
+            if t32[0]:
+                assert ref[1] == orc.SIDE_HIGH and ref[2] < 2.0 ** -20
+            elif ref[1] == orc.SIDE_HIGH:
+                assert ref[2] >= 2.0 ** -20 - 2.0 ** -54
 
 
 def test_tail_probability_is_two_to_minus_20(orc):
-    """16 of the 2^24 cells take the tail: count them exactly."""
-    tails = sum(orc.speed_uniform(orc.MODE_FP32, (m << 8), 0)[0] for m in range((1 << 24) - 64, 1 << 24))
-    assert tails == 16 and 16 / 2 ** 24 == 2.0 ** -20
+    """The top 2^12 of the 2^32 values of r0 take the tail: count them exactly."""
+    tails = sum(orc.speed_uniform(orc.MODE_FP32, r0, 0)[0] for r0 in range((1 << 32) - (1 << 14), 1 << 32, 4))
+    assert tails * 4 == 1 << 12 and (1 << 12) / 2 ** 32 == 2.0 ** -20
     # the oracle's sampler counts about N 2^-20 tail particles
     n = 1 << 22
     *_, t = orc.sample(1.6, 1.0, n, 5, mode=orc.MODE_FP32)
