@@ -26,6 +26,13 @@ METRIC = "particles/sec (3D velocities) and % HBM-write roofline vs same-GPU exa
 KERNEL_SOURCES = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/forward.hip",
                   "paper_2602_05606_amd/csrc/kappa_params.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_fp32_c2.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_forward_fp32_c2.json")
+# VALU issue capacity: 256 CUs x 4 SIMDs x 2.4 GHz.  A wave64 full-rate FP32
+# instruction occupies a SIMD for 2 cycles (the 157.3 TFLOP/s FP32 vector
+# peak); transcendentals and 32x32->64 integer multiplies run at a quarter of
+# that rate (8 cycles; measured 8.9 on the chip).
+SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9
+CYCLES_FULL, CYCLES_QUARTER = 2, 8
 
 
 def log(msg):
@@ -52,6 +59,26 @@ def measured_traffic(launch_bytes):
         return None
     return {"write_bytes": t["write_bytes_per_launch"], "fetch_bytes": t["fetch_bytes_per_launch"],
             "algorithmic_bytes": launch_bytes, "calibration": t.get("calibration")}
+
+
+def alu_roofline(particles_per_s):
+    """VALU-issue roofline of the dominant kernel from its measured instruction
+    counts (rocprofv3 SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32 and the static
+    v_mad_u64_u32 count), or None when they were taken on other kernel sources."""
+    try:
+        with open(VALU_FILE) as f:
+            v = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if v.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    quarter = v["trans_per_particle"] + v["mad_u64_per_particle"]
+    full = v["valu_per_particle"] - quarter
+    cycles_per_particle = (CYCLES_FULL * full + CYCLES_QUARTER * quarter) / 64.0
+    achieved = particles_per_s * cycles_per_particle
+    return {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
+            "frac": achieved / SIMD_CYCLES_PER_S, "valu_per_particle": v["valu_per_particle"],
+            "quarter_rate_per_particle": quarter, "simd_cycles_per_particle": cycles_per_particle}
 
 
 def time_launches(fn, reps, torch):
@@ -201,6 +228,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
                      "kernel": "forward_kernel<FP32 tail, 4 particles/thread>",
                      "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
+        "roofline_alu": alu_roofline(n / (avg_kernel_ms * 1e-3)),
     }
 
     if args.calibrate:
@@ -290,9 +318,13 @@ def main():
                 plan.graph_launch(outb)
             torch.cuda.synchronize()
             wall_ms = (time.perf_counter() - t0) * 1e3 / 50
+            # the single-species kernel on the same number of particles, for comparison
+            single_ms = time_launches(lambda: kp.sample(3.0, 1.0, plan.total, 4, precision=kp.FP32, out=outb), 20,
+                                      torch)
             extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
                                     "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
-                                    "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3)}
+                                    "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),
+                                    "single_species_same_size_ms": single_ms}
         log("batched done")
         result["extras"] = extras
     if not args.no_cpu_baseline:

@@ -13,6 +13,8 @@
 // The kernel reads the upstream gradient (3 x sizeof(T) bytes per particle)
 // and writes one pair of FP64 partial sums per block; a second one-block
 // kernel adds the partials in a fixed order.
+#include <cstdlib>
+
 #include "kappa_device.hpp"
 #include "kappa_internal.hpp"
 
@@ -58,9 +60,8 @@ __device__ __forceinline__ void load_group(const T *p, T (&v)[U])
 // d(v . g)/dkappa contribution in FP64 for one particle (FP64 mode, FP32 tail).
 __device__ __forceinline__ double dk_term_f64(const InvF64 &inv, const SpeciesF64 &s, double vg)
 {
-    const double ez = exp(inv.z);
-    const double dL = -expm1(inv.z) + inv.z * ez;
-    const double x = inv.x;
+    const double dL = fma(inv.z, inv.ez, -inv.em1);  // z e^z - expm1(z)
+    const double x = inv.x();
     const double num = fma(s.db * x, x, fma(fma(s.dc, inv.L, s.da) + s.c * dL, x, dL));
     return vg * (-num / inv.D) / (2.0 * x);
 }
@@ -109,6 +110,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
         }
         uint32_t tails = 0;
         float tail_dot[U];
+        float grp_s = 0.0f, grp_k = 0.0f;  // FP32 sums of this group's U terms
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             tail_dot[k] = 0.0f;
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                 speed_uniform_f64(b.r0, b.r3, high, u);
                 const InvF64 inv = invert_f64(high, u, a.s64);
                 const DirF64 d = direction_f64(b.r1, b.r2);
-                const double V = a.s64.theta * sqrt(inv.x);
+                const double V = a.s64.theta * inv.sqrt_x();
                 const double vg = V * (d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k]);
                 acc_s += vg;
                 acc_k += dk_term_f64(inv, a.s64, vg);
@@ -140,10 +142,14 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                     const float dL = dL_dkappa_f32(inv);
                     const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
                     const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
-                    acc_s += static_cast<double>(vg);
-                    acc_k += static_cast<double>(term);
+                    grp_s += vg;
+                    grp_k += term;
                 }
             }
+        }
+        if constexpr (MODE != kModeF64) {
+            acc_s += static_cast<double>(grp_s);
+            acc_k += static_cast<double>(grp_k);
         }
         if constexpr (MODE == kModeF32) {
             // rare: 1 - U1 < 2^-20, the speed comes from the FP64 inversion
@@ -157,7 +163,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                         speed_uniform_f64(b.r0, b.r3, h64, u64);
                         const InvF64 i64 = invert_f64(h64, u64, a.s64);
                         // the sampler's output speed is the FP64 speed rounded to float
-                        const double V = static_cast<double>(static_cast<float>(a.s64.theta * sqrt(i64.x)));
+                        const double V = static_cast<double>(static_cast<float>(a.s64.theta * i64.sqrt_x()));
                         const double vg = V * static_cast<double>(tail_dot[k]);
                         acc_s += vg;
                         acc_k += dk_term_f64(i64, a.s64, vg);
@@ -187,19 +193,21 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
     }
 }
 
-__global__ void __launch_bounds__(kBwdBlock) backward_finalize(const double *partials, int nblocks,
+constexpr int kFinBlock = 1024;
+
+__global__ void __launch_bounds__(kFinBlock) backward_finalize(const double *partials, int nblocks,
                                                                double inv_theta, double *grad)
 {
     double sk = 0.0, ss = 0.0;
-    for (int j = threadIdx.x; j < nblocks; j += kBwdBlock) {
+    for (int j = threadIdx.x; j < nblocks; j += kFinBlock) {
         sk += partials[2 * j];
         ss += partials[2 * j + 1];
     }
-    __shared__ double red[2][kBwdBlock];
+    __shared__ double red[2][kFinBlock];
     red[0][threadIdx.x] = sk;
     red[1][threadIdx.x] = ss;
     __syncthreads();
-    for (int w = kBwdBlock / 2; w > 0; w >>= 1) {
+    for (int w = kFinBlock / 2; w > 0; w >>= 1) {
         if (static_cast<int>(threadIdx.x) < w) {
             red[0][threadIdx.x] += red[0][threadIdx.x + w];
             red[1][threadIdx.x] += red[1][threadIdx.x + w];
@@ -232,12 +240,20 @@ hipError_t launch_mode(const BwdArgs &a, bool vec, hipStream_t stream)
 }  // namespace
 
 // Fixed for a given n (independent of the device) so the summation order, and
-// hence the result, is reproducible.
+// hence the result, is reproducible.  KAPPA_BACKWARD_GRID=<blocks> overrides
+// the cap for tuning (0: one thread per group, up to 2^20 blocks); a
+// different grid changes only the order of the FP64 sums.
 int backward_grid(uint64_t n)
 {
     const uint64_t per_block = static_cast<uint64_t>(kBwdBlock) * 4;
     const uint64_t need = (n + per_block - 1) / per_block;
-    return static_cast<int>(need < 1 ? 1 : (need > kBwdMaxGrid ? kBwdMaxGrid : need));
+    uint64_t cap = kBwdMaxGrid;
+    if (const char *env = std::getenv("KAPPA_BACKWARD_GRID")) {
+        const long v = std::strtol(env, nullptr, 10);
+        if (v == 0) cap = 1u << 20;
+        else if (v > 0 && v <= (1 << 20)) cap = static_cast<uint64_t>(v);
+    }
+    return static_cast<int>(need < 1 ? 1 : (need > cap ? cap : need));
 }
 
 hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStream_t stream)
@@ -254,7 +270,7 @@ hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStrea
     default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(backward_finalize, dim3(1), dim3(kBwdBlock), 0, stream, args.partials,
+    hipLaunchKernelGGL(backward_finalize, dim3(1), dim3(kFinBlock), 0, stream, args.partials,
                        backward_grid(args.n), 1.0 / args.s64.theta, grad);
     return hipGetLastError();
 }

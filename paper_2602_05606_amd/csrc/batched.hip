@@ -83,6 +83,24 @@ __device__ __forceinline__ void store_group_b(T *p, const T (&v)[U])
     }
 }
 
+// A group's U particles usually lie in one segment (C4's segments hold about
+// 420 particles): the segment's bounds, id and setup block are loaded once
+// per group and reloaded only where the group crosses into the next segment.
+template <int MODE>
+struct SegParams;
+
+template <>
+struct SegParams<kModeF64> {
+    SegF64 q;
+    __device__ __forceinline__ void load(const BatchArgs &a, uint32_t s) { q = a.seg64[s]; }
+};
+
+template <int MODE>
+struct SegParams {
+    SegF32 q;
+    __device__ __forceinline__ void load(const BatchArgs &a, uint32_t s) { q = a.seg32[s]; }
+};
+
 template <int MODE, int U>
 __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
 {
@@ -96,6 +114,10 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
         const uint64_t j0 = g * U;
         const uint64_t t = j0 / kTile;
         uint32_t s = find_segment(a.start, a.tile[t], a.tile[t + 1], j0);
+        uint64_t seg_begin = a.start[s], seg_next = a.start[s + 1];  // s + 1 <= nseg
+        uint32_t seg_id = a.seg_ids[s];
+        SegParams<MODE> prm;
+        prm.load(a, s);
         T x[U], y[U], z[U];
         uint32_t seg_of[U];
         uint32_t tails = 0;
@@ -107,19 +129,23 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 seg_of[k] = s;
                 continue;
             }
-            while (s + 1 < a.nseg && a.start[s + 1] <= j) ++s;
+            if (j >= seg_next) {
+                // next non-empty segment; ends because j < total = start[nseg]
+                do {
+                    ++s;
+                    seg_next = a.start[s + 1];
+                } while (j >= seg_next);
+                seg_begin = a.start[s];
+                seg_id = a.seg_ids[s];
+                prm.load(a, s);
+            }
             seg_of[k] = s;
-            const uint64_t local = j - a.start[s];
-            const Block4 b = particle_block(local, a.seg_ids[s], 0, a.k0, a.k1);
+            const Block4 b = particle_block(j - seg_begin, seg_id, 0, a.k0, a.k1);
+            const auto &q = prm.q;
             if constexpr (MODE == kModeF64) {
-                const SegF64 q = a.seg64[s];
                 SpeciesF64 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.half_inv_b, q.theta, 0, 0, 0};
                 particle_f64(b, sp, x[k], y[k], z[k]);
-                x[k] += q.dx;
-                y[k] += q.dy;
-                z[k] += q.dz;
             } else {
-                const SegF32 q = a.seg32[s];
                 SpeciesF32 sp{};
                 sp.kstar = q.kstar;
                 sp.inv_kstar = q.inv_kstar;
@@ -130,22 +156,22 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 sp.four_b = q.four_b;
                 sp.theta = q.theta;
                 particle_f32(b, sp, x[k], y[k], z[k]);
-                x[k] += q.dx;
-                y[k] += q.dy;
-                z[k] += q.dz;
                 if constexpr (MODE == kModeF32) tails |= static_cast<uint32_t>(in_fp64_tail(b.r0)) << k;
             }
+            x[k] += q.dx;
+            y[k] += q.dy;
+            z[k] += q.dz;
         }
         if constexpr (MODE == kModeF32) {
             if (__builtin_expect(tails != 0, 0)) {
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     if ((tails >> k) & 1u) {
-                        const uint32_t q = seg_of[k];
-                        const SegF64 w = a.seg64[q];
-                        const SegF32 f = a.seg32[q];
+                        const uint32_t sq = seg_of[k];
+                        const SegF64 w = a.seg64[sq];
+                        const SegF32 f = a.seg32[sq];
                         const SpeciesF64 s64{w.kstar, w.inv_kstar, w.a, w.b, w.c, w.half_inv_b, w.theta, 0, 0, 0};
-                        const Block4 b = particle_block(j0 + k - a.start[q], a.seg_ids[q], 0, a.k0, a.k1);
+                        const Block4 b = particle_block(j0 + k - a.start[sq], a.seg_ids[sq], 0, a.k0, a.k1);
                         tail_particle_f32(b, s64, x[k], y[k], z[k]);
                         x[k] += f.dx;
                         y[k] += f.dy;

@@ -71,33 +71,143 @@ __device__ __forceinline__ Block4 particle_block(uint64_t i, uint32_t seg, uint3
 // ln(y) + d/y, which is how one log call serves both sides.
 // ---------------------------------------------------------------------------
 
+// e^p and e^p - 1 from one argument reduction (the textbook method: Cody and
+// Waite's two-part ln 2, then a polynomial on |r| <= ln2/2): p = k ln2 + r,
+// q = expm1(r) by its Taylor series to r^13 (truncation < 2e-17 relative),
+// e^p = 2^k (1 + q), e^p - 1 = 2^k q + (2^k - 1).  The last form has no
+// harmful cancellation for any k (|q| <= 0.42).
+__device__ __forceinline__ void exp_expm1_f64(double p, double &e, double &em1)
+{
+    constexpr double kLog2e = 0x1.71547652b82fep+0;
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
+    const double k = rint(p * kLog2e);
+    double r = fma(-k, kLn2Hi, p);
+    r = fma(-k, kLn2Lo, r);
+    double t = 1.0 / 6227020800.0;            // 1/13!
+    t = fma(t, r, 1.0 / 479001600.0);         // 1/12!
+    t = fma(t, r, 1.0 / 39916800.0);
+    t = fma(t, r, 1.0 / 3628800.0);
+    t = fma(t, r, 1.0 / 362880.0);
+    t = fma(t, r, 1.0 / 40320.0);
+    t = fma(t, r, 1.0 / 5040.0);
+    t = fma(t, r, 1.0 / 720.0);
+    t = fma(t, r, 1.0 / 120.0);
+    t = fma(t, r, 1.0 / 24.0);
+    t = fma(t, r, 1.0 / 6.0);
+    t = fma(t, r, 0.5);
+    t = fma(t, r, 1.0);
+    const double q = r * t;                   // expm1(r)
+    const int ki = static_cast<int>(k);
+    e = ldexp(1.0 + q, ki);
+    em1 = fma(q, ldexp(1.0, ki), ldexp(1.0, ki) - 1.0);
+}
+
+// Natural log of x in (0, 1] (normal doubles), within a few ulp: x = m 2^e
+// with m in [sqrt(1/2), sqrt(2)), f = m - 1 (exact), and
+// log(1 + f) = 2 atanh(s) = 2s + 2s^3/3 + 2s^5/5 + ..., s = f / (2 + f),
+// |s| <= 0.172; the series is summed to s^21 (truncation < 1e-17 relative).
+// The division is one v_rcp_f64 step refined by a Newton correction.
+__device__ __forceinline__ double log_unit_f64(double x)
+{
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
+    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool low = m < 0x1.6a09e667f3bcdp-1;   // sqrt(1/2)
+    m = low ? 2.0 * m : m;
+    e = low ? e - 1 : e;
+    const double f = m - 1.0;
+    const double den = 2.0 + f;
+    const double rc = __builtin_amdgcn_rcp(den);
+    double sv = f * rc;
+    sv = fma(fma(-sv, den, f), rc, sv);          // one Newton correction of f / den
+    const double z = sv * sv;
+    double q = 2.0 / 21.0;
+    q = fma(q, z, 2.0 / 19.0);
+    q = fma(q, z, 2.0 / 17.0);
+    q = fma(q, z, 2.0 / 15.0);
+    q = fma(q, z, 2.0 / 13.0);
+    q = fma(q, z, 2.0 / 11.0);
+    q = fma(q, z, 2.0 / 9.0);
+    q = fma(q, z, 2.0 / 7.0);
+    q = fma(q, z, 2.0 / 5.0);
+    q = fma(q, z, 2.0 / 3.0);
+    const double ed = static_cast<double>(e);
+    const double lo = fma(ed, kLn2Lo, sv * z * q);
+    return fma(ed, kLn2Hi, fma(2.0, sv, lo));
+}
+
+// sin(pi x) and cos(pi x) for x = (2 r + 1) 2^-32 in (0, 2), exact in double:
+// n = rint(2x), r = x - n/2 in [-1/4, 1/4] (exact), Taylor series of
+// sin(pi r) to (pi r)^17 and of cos(pi r) to (pi r)^18 (truncation below
+// 1e-19), then the quadrant n mod 4 swaps and signs the pair.
+__device__ __forceinline__ void sincospi_f64(double x, double &sn, double &cs)
+{
+    const double n = rint(2.0 * x);
+    const double r = fma(-0.5, n, x);
+    const double t = r * 0x1.921fb54442d18p+1;   // pi r, |t| <= pi/4
+    const double t2 = t * t;
+    double ps = -1.0 / 355687428096000.0;        // -1/17!
+    ps = fma(ps, t2, 1.0 / 1307674368000.0);     // 1/15!
+    ps = fma(ps, t2, -1.0 / 6227020800.0);
+    ps = fma(ps, t2, 1.0 / 39916800.0);
+    ps = fma(ps, t2, -1.0 / 362880.0);
+    ps = fma(ps, t2, 1.0 / 5040.0);
+    ps = fma(ps, t2, -1.0 / 120.0);
+    ps = fma(ps, t2, 1.0 / 6.0);
+    const double sr = fma(-t * t2, ps, t);       // sin(pi r)
+    double pc = 1.0 / 6402373705728000.0;        // 1/18!
+    pc = fma(pc, t2, -1.0 / 20922789888000.0);   // -1/16!
+    pc = fma(pc, t2, 1.0 / 87178291200.0);
+    pc = fma(pc, t2, -1.0 / 479001600.0);
+    pc = fma(pc, t2, 1.0 / 3628800.0);
+    pc = fma(pc, t2, -1.0 / 40320.0);
+    pc = fma(pc, t2, 1.0 / 720.0);
+    pc = fma(pc, t2, -1.0 / 24.0);
+    pc = fma(pc, t2, 0.5);
+    const double cr = fma(-t2, pc, 1.0);         // cos(pi r)
+    const int q = static_cast<int>(n) & 3;
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    sn = (q & 2) ? -a : a;
+    cs = ((q + 1) & 2) ? -b : b;
+}
+
 struct InvF64 {
-    double z;  // -lT / kappa*
-    double L;  // q-logarithm of 1 - U1^{2/3}
-    double D;  // sqrt(A^2 - 4bL)
-    double x;  // (V/theta)^2
+    double z;    // -lT / kappa*
+    double ez;   // e^z
+    double em1;  // e^z - 1
+    double L;    // q-logarithm of 1 - U1^{2/3}
+    double D;    // sqrt(A^2 - 4bL)
+    double num, den;  // x = (V/theta)^2 = num / den, both > 0
+    __device__ __forceinline__ double x() const { return num / den; }
+    __device__ __forceinline__ double sqrt_x() const { return num * rsqrt(num * den); }
 };
 
 __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF64 &s)
 {
-    // l1 = ln U1.  High side: U1 = 1 - u = y1 + d1 exactly, y1 = fl(1 - u).
+    // l1 = ln U1.  High side: U1 = 1 - u = y1 + d1 exactly, y1 = fl(1 - u); the
+    // correction d1/y1 is taken as d1 (|d1| <= 2^-54 and y1 >= 1/2, so this
+    // changes ln U1 by less than 2^-53 relative).
     const double y1 = high ? 1.0 - u : u;
     const double d1 = high ? (1.0 - y1) - u : 0.0;
-    const double l1 = log(y1) + d1 / y1;
+    const double l1 = log_unit_f64(y1) + d1;
     const double p = (2.0 / 3.0) * l1;
     // 1 - U1^{2/3} = y2 + d2.  Low side: t = e^p, y2 = fl(1 - t), d2 = (1 - y2) - t.
     // High side: y2 = -expm1(p), d2 = 0.
-    const double t = exp(p);
-    const double em1 = expm1(p);
+    double t, em1;
+    exp_expm1_f64(p, t, em1);
     const double y2 = high ? -em1 : 1.0 - t;
     const double d2 = high ? 0.0 : (1.0 - y2) - t;
-    const double lT = log(y2) + d2 / y2;
+    const double lT = log_unit_f64(y2) + d2;
     InvF64 r;
     r.z = -lT * s.inv_kstar;
-    r.L = -s.kstar * expm1(r.z);
+    exp_expm1_f64(r.z, r.ez, r.em1);
+    r.L = -s.kstar * r.em1;
     const double A = fma(s.c, r.L, s.a);
     r.D = sqrt(fma(A, A, -4.0 * s.b * r.L));
-    r.x = (A >= 0.0) ? (-2.0 * r.L) / (A + r.D) : (r.D - A) * s.half_inv_b;
+    const bool pos = A >= 0.0;
+    r.num = pos ? -2.0 * r.L : r.D - A;
+    r.den = pos ? A + r.D : 2.0 * s.b;
     return r;
 }
 
@@ -205,7 +315,7 @@ __device__ __forceinline__ DirF64 direction_f64(uint32_t r1, uint32_t r2)
     const double st = sqrt((1.0 - ct) * (1.0 + ct));  // both factors exact
     const double u3x2 = static_cast<double>(2 * static_cast<uint64_t>(r2) + 1) * 0x1p-32;  // 2 U3
     double sp, cp;
-    sincospi(u3x2, &sp, &cp);
+    sincospi_f64(u3x2, sp, cp);
     DirF64 d;
     d.cx = ct;
     d.cy = st * cp;
@@ -247,7 +357,7 @@ __device__ __forceinline__ void particle_f64(const Block4 &b, const SpeciesF64 &
     double u;
     speed_uniform_f64(b.r0, b.r3, high, u);
     const InvF64 inv = invert_f64(high, u, s);
-    const double V = s.theta * sqrt(inv.x);
+    const double V = s.theta * inv.sqrt_x();
     const DirF64 d = direction_f64(b.r1, b.r2);
     vx = V * d.cx;
     vy = V * d.cy;
@@ -279,7 +389,7 @@ __device__ __forceinline__ void tail_particle_f32(const Block4 &b, const Species
     double u;
     speed_uniform_f64(b.r0, b.r3, high, u);
     const InvF64 inv = invert_f64(high, u, s64);
-    const float V = static_cast<float>(s64.theta * sqrt(inv.x));
+    const float V = static_cast<float>(s64.theta * inv.sqrt_x());
     const DirF32 d = direction_f32(b.r1, b.r2);
     vx = V * d.cx;
     vy = V * d.cy;
