@@ -136,6 +136,73 @@ def ks_table(kp, torch, kappas, theta, seed, out32, n_ks=10 ** 7):
     return res
 
 
+def relative_entropy_test2(kp, torch, dev, kappas=(3.0, 4.1, 7.5), n_max=10 ** 10, chunk=10 ** 8, seed=3):
+    """The paper's second test (Sec. 5, eq:KL, Fig. fig:KL) at N = 1e6 .. n_max:
+    D(P||Q) between the exact Kappa speed bins (width theta/5) and the Monte
+    Carlo histogram, for the approximate generator (one counter stream,
+    accumulated) and the exact t generator (one seed per chunk), with the
+    time the GPU spent generating and binning."""
+    import numpy as np
+    checkpoints = [10 ** e for e in range(6, int(round(np.log10(n_max))) + 1)]
+    buf = tuple(torch.empty(chunk, dtype=torch.float32, device=dev) for _ in range(3))
+    res = {"bin_width": 0.2, "nbins": 100, "eps": 1e-10, "N": checkpoints}
+    for k in kappas:
+        row = {}
+        for name in ("approx", "t_gamma"):
+            counts = torch.zeros(101, dtype=torch.int64, device=dev)
+            done, ds = 0, []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for target in checkpoints:
+                while done < target:
+                    m = min(chunk, target - done)
+                    sub = tuple(b[:m] for b in buf)
+                    if name == "approx":
+                        kp.sample(k, 1.0, m, seed, counter_offset=done, precision=kp.FP32, out=sub)
+                    else:
+                        kp.sample_exact_t(k, 1.0, m, seed + 1000 + done // chunk, precision=kp.FP32, out=sub)
+                    kp.speed_histogram(*sub, theta=1.0, bin_width=0.2, nbins=100, counts=counts)
+                    done += m
+                ds.append(kp.relative_entropy(k, counts, 0.2))
+            torch.cuda.synchronize()
+            row[name] = ds
+            row[name + "_s"] = time.perf_counter() - t0
+        res[str(k)] = row
+    h_ms = time_launches(lambda: kp.speed_histogram(*buf, theta=1.0, bin_width=0.2, nbins=100), 5, torch)
+    res["histogram_GB_per_s_read"] = 12 * chunk / (h_ms * 1e-3) / 1e9
+    return res
+
+
+def divergence_survey(kp, torch, dev):
+    """The grid search behind eq:c (Sec. 3, Fig. fig:map): D(f||g; kappa, c) on
+    c in [0, 1.5] x kappa in (1.5, 10] at steps 0.005 and 0.01, with the
+    optimum c per kappa, and D and the energy error along eq:c (Fig. fig:DE)."""
+    import numpy as np
+    ks = np.round(np.arange(1.51, 10.0001, 0.01), 10)
+    cs = np.round(np.arange(0.0, 1.5001, 0.005), 10)
+    kt = torch.tensor(ks, dtype=torch.float64, device=dev)
+    ct = torch.tensor(cs, dtype=torch.float64, device=dev)
+    D = torch.empty((len(ks), len(cs)), dtype=torch.float64, device=dev)
+    am = torch.empty(len(ks), dtype=torch.int32, device=dev)
+    kp.divergence_grid(kt, ct, energy=False, argmin=True)  # warm-up
+    ms = time_launches(lambda: kp._lib.check(kp._lib.load().kappa_divergence_grid(
+        kp._ptr(kt), len(ks), kp._ptr(ct), len(cs), kp._ptr(D), None, kp._ptr(am),
+        kp._stream(None, dev)), "kappa_divergence_grid"), 3, torch)
+    copt = cs[am.cpu().numpy()]
+    dc, ec, _ = kp.divergence_grid(kt, None)
+    dc, ec = dc.cpu().numpy()[:, 0], ec.cpu().numpy()[:, 0]
+    pick = [1.6, 2.0, 2.6, 3.0, 3.5, 3.9, 4.1, 4.2, 5.0, 7.5, 10.0]
+    idx = [int(np.argmin(np.abs(ks - k))) for k in pick]
+    points = len(ks) * len(cs)
+    return {"kappa_points": len(ks), "c_points": len(cs), "ms": ms, "grid_points_per_s": points / (ms * 1e-3),
+            "quadrature_nodes": 192,
+            "optimum_c": {str(pick[n]): float(copt[i]) for n, i in enumerate(idx)},
+            "D_along_eq_c": {str(pick[n]): float(dc[i]) for n, i in enumerate(idx)},
+            "dE_over_E_along_eq_c": {str(pick[n]): float(ec[i]) for n, i in enumerate(idx)},
+            "kappa_where_optimum_c_leaves_the_range": [float(ks[i]) for i in np.nonzero(copt == cs[-1])[0][[0, -1]]]
+            if np.any(copt == cs[-1]) else None}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (FP64 arithmetic at the FP32 mode's uniforms, OpenMP over
     particles) timed on the host over a bounded sample of the C2 workload."""
@@ -268,6 +335,10 @@ def main():
         log("exact generators done")
         extras["ks_vs_exact_cdf"] = ks_table(kp, torch, kappas, theta, seed, out32)
         log("KS distances done")
+        extras["relative_entropy_test2"] = relative_entropy_test2(kp, torch, dev)
+        log("relative-entropy test done")
+        extras["divergence_survey"] = divergence_survey(kp, torch, dev)
+        log("divergence survey done")
         c5 = workloads.C5
         chunk_out = tuple(t[:c5["chunk"]] for t in out32) if c5["chunk"] <= n else None
         if chunk_out is None:

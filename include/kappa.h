@@ -218,6 +218,53 @@ KAPPA_API kappa_status kappa_sample_exact_t(double kappa, double theta, uint64_t
 KAPPA_API kappa_status kappa_sample_exact_pareto(double kappa, double theta, uint64_t n, uint64_t seed, int precision,
                                        void *vx, void *vy, void *vz, uint32_t *iters, void *stream);
 
+/* kappa_speed_histogram -- data of the Monte Carlo relative-entropy test
+ * (Sec. 5, second test, eq:KL): adds to counts[k] the number of particles
+ * whose speed |v| lies in [k w theta, (k+1) w theta), k < nbins, and to
+ * counts[nbins] those at or beyond nbins w theta (w = bin_width).
+ * Membership is decided exactly: bin k holds edge2[k] <= s2 < edge2[k+1],
+ * with s2 = (vx*vx + vy*vy) + vz*vz evaluated in the data's precision and
+ * edge2[k] = (k * (w * theta))^2 computed in FP64 and rounded once to that
+ * precision, so any IEEE implementation of this definition gets the same
+ * counts.
+ *   vx, vy, vz  device arrays of n velocities (double for KAPPA_FP64, float
+ *               for KAPPA_FP32 / KAPPA_FP32_NOTAIL), read only.
+ *   counts      device array of nbins + 1 uint64, accumulated (not cleared),
+ *               8-byte aligned.
+ * 1 <= nbins <= 2047 and n <= 2^40 (else KAPPA_ERANGE); theta and bin_width
+ * positive and finite (else KAPPA_EINVAL).  Asynchronous. */
+KAPPA_API kappa_status kappa_speed_histogram(const void *vx, const void *vy, const void *vz, uint64_t n, int precision,
+                                             double theta, double bin_width, uint32_t nbins, uint64_t *counts,
+                                             void *stream);
+
+/* kappa_divergence_grid -- quality of the approximation G (Sec. 3, eq:G)
+ * against the Kappa distribution over a grid of (kappa, c), as in the grid
+ * search behind eq:c (Sec. 3, eq:relative_entropy, Fig. fig:map) and the
+ * energy comparison of Fig. fig:DE(b).  For each kappa_i and c_j, with a, b/c
+ * and kappa* of Table 1 and b = (b/c) c_j:
+ *   D[i*nc + j]  = int_0^inf f ln(f/g) dx          (eq:relative_entropy)
+ *   dE[i*nc + j] = (E_approx - E_kappa) / E_kappa  (eq:kappaE, Fig. fig:DE)
+ * with f of eq:kappax and g of eq:approx_x.  Integrals by an exp-sinh rule of
+ * 192 nodes over x in [1e-61, 1e291]; against 30-digit quadrature of the
+ * definitions the rule is within 1e-12 relative for D and 1e-14 absolute for
+ * dE (for c = 0 the energy tail decays like x^(1/2 - kappa), so dE is only
+ * settled for kappa >= 1.6 there).
+ *   kappa   device array of nk doubles.  Entries that are not finite or not
+ *           above 3/2 give NaN rows.
+ *   c       device array of nc doubles (c >= 0; other entries give NaN), or
+ *           NULL with nc = 1 to take c from eq:c for each kappa (the paper's
+ *           curve of Fig. fig:DE).
+ *   D       device array of nk*nc doubles, written (row i = kappa_i).
+ *   dE      device array of nk*nc doubles, written; NULL to skip.
+ *   argmin  device array of nk uint32, written with the j of the smallest
+ *           D in row i (NaN skipped, lowest j on ties, 0xFFFFFFFF if none);
+ *           NULL to skip.
+ * nk <= 65535 and nc <= 2^24 (else KAPPA_ERANGE); 8-byte aligned doubles,
+ * 4-byte aligned argmin (else KAPPA_EALIGN).  nk = 0 or nc = 0 is a no-op.
+ * Asynchronous. */
+KAPPA_API kappa_status kappa_divergence_grid(const double *kappa, uint32_t nk, const double *c, uint32_t nc,
+                                             double *D, double *dE, uint32_t *argmin, void *stream);
+
 /* Measurement probes.
  * kappa_fill_probe: store-only kernel writing the constant pattern 1, 2, 3 to
  *   vx, vy, vz (n elements of the precision's type) with the generator's store

@@ -65,6 +65,10 @@ def _load():
     lib.oracle_find_tails.restype = c_u64
     lib.oracle_dot.argtypes = [c_d, c_d, c_u64, c_u64, c_u64, c_u32, c_int, fp, fp, fp]
     lib.oracle_dot.restype = c_d
+    lib.oracle_speed_histogram_f32.argtypes = [fp, fp, fp, c_u64, c_d, c_d, c_u32, u64p]
+    lib.oracle_speed_histogram_f32.restype = None
+    lib.oracle_speed_histogram_f64.argtypes = [dp, dp, dp, c_u64, c_d, c_d, c_u32, u64p]
+    lib.oracle_speed_histogram_f64.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = c_int
     lib.oracle_set_num_threads.argtypes = [c_int]
@@ -188,6 +192,23 @@ def dot(kappa, theta, n, seed, gx, gy, gz, counter_offset=0, seg=0, mode=MODE_FP
     assert gx.size == n and gy.size == n and gz.size == n
     return _load().oracle_dot(float(kappa), float(theta), n, seed, counter_offset, seg, mode,
                               _ptr(gx, ctypes.c_float), _ptr(gy, ctypes.c_float), _ptr(gz, ctypes.c_float))
+
+
+def speed_histogram(vx, vy, vz, theta, bin_width, nbins, counts=None):
+    """Counts of |v| per bin (nbins + 1 uint64, the last the overflow), in the
+    precision of the arrays (float32 or float64)."""
+    lib = _load()
+    if counts is None:
+        counts = np.zeros(nbins + 1, dtype=np.uint64)
+    if np.asarray(vx).dtype == np.float32:
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (vx, vy, vz)]
+        lib.oracle_speed_histogram_f32(*[_ptr(v, ctypes.c_float) for v in a], a[0].size, float(theta),
+                                       float(bin_width), nbins, _ptr(counts, ctypes.c_uint64))
+    else:
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (vx, vy, vz)]
+        lib.oracle_speed_histogram_f64(*[_ptr(v, ctypes.c_double) for v in a], a[0].size, float(theta),
+                                       float(bin_width), nbins, _ptr(counts, ctypes.c_uint64))
+    return counts
 
 
 def num_threads():

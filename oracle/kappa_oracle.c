@@ -427,6 +427,70 @@ double oracle_dot(double kappa, double theta, uint64_t n, uint64_t seed, uint64_
     return sum;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Speed histogram for the Monte Carlo relative entropy of the paper's second
+ * test (Sec. 5, eq:KL): counts[k] += #{particles with
+ * edge2[k] <= s2 < edge2[k+1]} for k < nbins, counts[nbins] += the rest, where
+ * s2 = (vx*vx + vy*vy) + vz*vz in the data's precision and
+ * edge2[k] = (k * (bin_width * theta))^2 in FP64, rounded once to that
+ * precision.  Plain loop, binary search over the edges.                    */
+/* ------------------------------------------------------------------------ */
+static uint32_t bin_of_f32(const float *edge2, uint32_t nbins, float s2)
+{
+    uint32_t lo = 0, hi = nbins; /* edge2[lo] <= s2 holds for lo = 0 */
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (edge2[mid] <= s2)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+void oracle_speed_histogram_f32(const float *vx, const float *vy, const float *vz, uint64_t n, double theta,
+                                double bin_width, uint32_t nbins, uint64_t *counts)
+{
+    double width = bin_width * theta;
+    float edge2[2048];
+    for (uint32_t k = 0; k <= nbins; ++k) {
+        double e = (double)k * width;
+        edge2[k] = (float)(e * e);
+    }
+    for (uint64_t j = 0; j < n; ++j) {
+        float s2 = (vx[j] * vx[j] + vy[j] * vy[j]) + vz[j] * vz[j];
+        counts[bin_of_f32(edge2, nbins, s2)] += 1;
+    }
+}
+
+static uint32_t bin_of_f64(const double *edge2, uint32_t nbins, double s2)
+{
+    uint32_t lo = 0, hi = nbins;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (edge2[mid] <= s2)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+void oracle_speed_histogram_f64(const double *vx, const double *vy, const double *vz, uint64_t n, double theta,
+                                double bin_width, uint32_t nbins, uint64_t *counts)
+{
+    double width = bin_width * theta;
+    double edge2[2048];
+    for (uint32_t k = 0; k <= nbins; ++k) {
+        double e = (double)k * width;
+        edge2[k] = e * e;
+    }
+    for (uint64_t j = 0; j < n; ++j) {
+        double s2 = (vx[j] * vx[j] + vy[j] * vy[j]) + vz[j] * vz[j];
+        counts[bin_of_f64(edge2, nbins, s2)] += 1;
+    }
+}
+
 /* Number of worker threads the oracle's parallel loops use. */
 int oracle_num_threads(void)
 {

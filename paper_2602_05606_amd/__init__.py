@@ -18,7 +18,8 @@ from ._lib import FP32, FP32_NOTAIL, FP64, KappaError, Segment
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
-    "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path",
+    "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
+    "relative_entropy",
 ]
 
 
@@ -281,3 +282,62 @@ def copy_probe(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _lib.check(_lib.load().kappa_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)),
                "kappa_copy_probe")
+
+
+def speed_histogram(vx, vy, vz, theta, bin_width=0.2, nbins=100, counts=None, stream=None):
+    """Counts of |v| in bins [k w theta, (k+1) w theta), k < nbins, plus an
+    overflow bin (kappa_speed_histogram).  counts (int64 device tensor of
+    nbins + 1) is accumulated when given; a new zeroed one otherwise."""
+    torch = _torch()
+    n = vx.numel()
+    prec = FP64 if vx.dtype == torch.float64 else FP32
+    if counts is None:
+        counts = torch.zeros(nbins + 1, dtype=torch.int64, device=vx.device)
+    st = _lib.load().kappa_speed_histogram(_ptr(vx), _ptr(vy), _ptr(vz), n, prec, float(theta), float(bin_width),
+                                           nbins, _ptr(counts), _stream(stream, vx.device))
+    _lib.check(st, "kappa_speed_histogram")
+    return counts
+
+
+def divergence_grid(kappa, c=None, energy=True, argmin=False, device=None, stream=None):
+    """Relative entropy D(f||g; kappa, c) (eq:relative_entropy) and energy
+    error (E_approx - E_kappa)/E_kappa (Fig. fig:DE(b)) of the approximation
+    on the grid kappa x c (kappa_divergence_grid).  kappa and c are 1-D
+    sequences or float64 device tensors; c=None takes c from eq:c for each
+    kappa (one column).  Returns (D, dE or None, argmin or None) as device
+    tensors of shape (nk, nc), (nk, nc) and (nk,)."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else (
+        kappa.device if hasattr(kappa, "device") and kappa.is_cuda else torch.device("cuda"))
+    k = torch.as_tensor(kappa, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    cv = None if c is None else torch.as_tensor(c, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    nk, nc = k.numel(), (1 if cv is None else cv.numel())
+    D = torch.empty((nk, nc), dtype=torch.float64, device=dev)
+    dE = torch.empty((nk, nc), dtype=torch.float64, device=dev) if energy else None
+    am = torch.empty(nk, dtype=torch.int32, device=dev) if argmin else None
+    st = _lib.load().kappa_divergence_grid(_ptr(k), nk, _ptr(cv), nc, _ptr(D), _ptr(dE), _ptr(am),
+                                           _stream(stream, dev))
+    _lib.check(st, "kappa_divergence_grid")
+    return D, dE, am
+
+
+def relative_entropy(kappa, counts, bin_width=0.2, eps=1e-10):
+    """The paper's Monte Carlo relative entropy (eq:KL):
+    D(P||Q) = sum_i (P_i + eps) ln((P_i + eps) / (Q_i + eps)), with P_i the
+    exact Kappa probability of speed bin i (bins of width bin_width in units
+    of theta, the last one open-ended) and Q_i the fraction of the counts.
+    P_i is the difference of the exact CDF of eq:CDF at the bin edges, which is
+    the integral of eq:kappax over the bin.  Host-side post-processing of the
+    nbins + 1 counts (scipy's regularized incomplete beta)."""
+    import numpy as np
+    from scipy import special
+    c = counts.detach().cpu().numpy().astype(np.float64) if hasattr(counts, "detach") else np.asarray(counts, float)
+    nb = c.size - 1
+    x = (np.arange(nb + 1) * bin_width) ** 2
+    cdf = special.betainc(1.5, kappa - 0.5, x / (x + kappa))
+    p = np.empty(nb + 1)
+    p[:nb] = np.diff(cdf)
+    xe = x[-1]
+    p[nb] = special.betainc(kappa - 0.5, 1.5, kappa / (xe + kappa))  # 1 - F at the last edge
+    q = c / c.sum()
+    return float(np.sum((p + eps) * np.log((p + eps) / (q + eps))))

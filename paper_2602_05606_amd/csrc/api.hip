@@ -268,6 +268,48 @@ kappa_status kappa_sample_exact_pareto(double kappa, double theta, uint64_t n, u
     return check_hip(launch_exact_pareto(precision, a, static_cast<hipStream_t>(stream)), "exact Pareto kernel launch");
 }
 
+kappa_status kappa_speed_histogram(const void *vx, const void *vy, const void *vz, uint64_t n, int precision,
+                                   double theta, double bin_width, uint32_t nbins, uint64_t *counts, void *stream)
+{
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
+    if (!std::isfinite(bin_width) || !(bin_width > 0.0))
+        return fail(KAPPA_EINVAL, "bin_width must be finite and > 0 (got %g)", bin_width);
+    if (nbins < 1 || nbins > 2047) return fail(KAPPA_ERANGE, "nbins %u outside [1, 2047]", nbins);
+    if (n > (1ull << 40)) return fail(KAPPA_ERANGE, "n above 2^40 per call");
+    if (!counts) return fail(KAPPA_EINVAL, "null counts");
+    if (reinterpret_cast<uintptr_t>(counts) % 8) return fail(KAPPA_EALIGN, "counts must be 8-byte aligned");
+    if (n > 0 && (!vx || !vy || !vz)) return fail(KAPPA_EINVAL, "null velocity pointer with n > 0");
+    const size_t e = elem_size(precision);
+    if (n > 0 && (reinterpret_cast<uintptr_t>(vx) % e || reinterpret_cast<uintptr_t>(vy) % e ||
+                  reinterpret_cast<uintptr_t>(vz) % e))
+        return fail(KAPPA_EALIGN, "velocity pointers must be aligned to %zu bytes", e);
+    if (n == 0) return KAPPA_OK;
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_histogram(precision, vx, vy, vz, n, bin_width * theta, nbins, counts,
+                                      static_cast<hipStream_t>(stream)),
+                     "histogram kernel launch");
+}
+
+kappa_status kappa_divergence_grid(const double *kappa, uint32_t nk, const double *c, uint32_t nc, double *D,
+                                   double *dE, uint32_t *argmin, void *stream)
+{
+    if (nk > 65535u) return fail(KAPPA_ERANGE, "nk %u above 65535", nk);
+    if (nc > (1u << 24)) return fail(KAPPA_ERANGE, "nc %u above 2^24", nc);
+    if (!c && nc > 1) return fail(KAPPA_EINVAL, "c = NULL (c from eq:c) needs nc = 1 (got %u)", nc);
+    if (nk == 0 || nc == 0) return KAPPA_OK;
+    if (!kappa || !D) return fail(KAPPA_EINVAL, "null kappa or D");
+    auto mis = [](const void *p, uintptr_t a) { return p && reinterpret_cast<uintptr_t>(p) % a != 0; };
+    if (mis(kappa, 8) || mis(c, 8) || mis(D, 8) || mis(dE, 8))
+        return fail(KAPPA_EALIGN, "kappa, c, D and dE must be 8-byte aligned");
+    if (mis(argmin, 4)) return fail(KAPPA_EALIGN, "argmin must be 4-byte aligned");
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_divergence(kappa, nk, c, nc, D, dE, argmin, static_cast<hipStream_t>(stream)),
+                     "divergence kernel launch");
+}
+
 kappa_status kappa_fill_probe(uint64_t n, int precision, void *vx, void *vy, void *vz, void *stream)
 {
     if (precision != KAPPA_FP64 && precision != KAPPA_FP32)

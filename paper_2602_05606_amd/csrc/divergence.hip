@@ -1,0 +1,198 @@
+// divergence.hip -- how far the approximation G (Sec. 3, eq:G) is from the
+// Kappa distribution, over a grid of (kappa, c): the relative entropy
+// D(f||g; kappa, c) of eq:relative_entropy (the quantity the paper's grid
+// search over c in [0, 1.5] x kappa in [1.5, 10] minimises, Fig. fig:map) and
+// the energy error (E_approx - E_kappa)/E_kappa of Fig. fig:DE(b).
+//
+// For a free c the other parameters stay as Table 1 sets them: a of eq:a,
+// kappa* of eq:k2, b = (b/c) c with b/c of eq:b.  f is eq:kappax and g is
+// eq:approx_x, both in x = v^2/theta^2.
+//
+// Quadrature.  x = exp(ell), ell = (pi/2) sinh(t) (the exp-sinh rule for
+// [0, inf)), trapezoidal in t with step 1/16 over t in [-83/16, 108/16]: 192
+// nodes, x from 1e-61 to 1e291.  With delta = ln g - ln f and since f and g
+// both integrate to one,
+//     D  = int f (e^delta - 1 - delta) dx,
+//     dE = int x f (e^delta - 1) dx / (3 kappa / (2 kappa - 3)),
+// where E_kappa = 3 kappa / (2 kappa - 3) in units of m theta^2 / 2 is
+// eq:kappaE.  Both integrands are sums of non-cancelling terms.  The first
+// form equals the printed definition int f ln(f/g) dx up to the truncation of
+// the range; it has no cancellation where f and g nearly agree, which is where
+// the paper's D of 1e-9..1e-5 comes from.
+//
+// Every evaluation stays finite for x up to 1e291: ln g is assembled from
+//   y   = (a + b x) * x / (1 + c x)
+//   s   = log1p(y / kappa*)             (1 + y/kappa*)^(-kappa*) = exp(-kappa* s)
+//   y'  = (a/x + 2b + b c x) * x / (1 + c x)^2,
+//   ln g = ln(3/2) + ln(1 - e^(-kappa* s))/2 - (kappa* + 1) s + ln y'.
+//
+// Work layout: one block per (kappa, group of c values); the block first
+// tabulates the c-independent part of every node (ell, x, 1/x, ln f and the
+// two quadrature weights) in LDS, then each wave takes one c at a time with
+// its 64 lanes over the nodes and reduces with a fixed butterfly, so results
+// do not depend on the launch shape.  The bound is FP64 VALU (five FP64
+// transcendentals per node); no HBM traffic beyond the outputs.
+#include <math.h>
+
+#include "kappa_internal.hpp"
+
+namespace kappa {
+
+namespace {
+
+constexpr int kDivNodes = 192;
+constexpr int kDivNeg = 83;  // nodes with t < 0
+constexpr double kDivH = 1.0 / 16.0;
+constexpr double kHalfPi = 1.5707963267948966;
+constexpr int kDivCPerBlock = 16;
+
+struct DivNode {
+    double x, q, lnf, w_d, w_e;  // x, 1/x, ln f(x), h (dx/dt) f, h (dx/dt) f x
+};
+
+struct KappaConst {
+    double kappa, kstar, lnB, a, b_over_c;
+    bool ok;
+};
+
+__device__ KappaConst kappa_const(double k)
+{
+    KappaConst s;
+    s.ok = isfinite(k) && k > 1.5;
+    s.kappa = k;
+    s.kstar = k - 0.5;                                                 // eq:k2
+    if (!s.ok) return s;
+    s.lnB = lgamma(1.5) + lgamma(s.kstar) - lgamma(k + 1.0);           // B(3/2, kappa - 1/2)
+    s.a = exp(-log(k) + (2.0 / 3.0) * (log(2.0 / 3.0) - s.lnB));       // eq:a
+    s.b_over_c = exp((log(1.5 * s.kstar) + s.lnB) / s.kstar) * s.kstar / k;  // eq:b
+    return s;
+}
+
+__device__ double c_from_eq_c(double k)
+{
+    return (0.123 * k * k - 1.12 * k + 2.56) / (k * k - 7.89 * k + 15.6);  // eq:c
+}
+
+// e^d - 1 - d and e^d - 1 without cancellation for small d (Taylor series to
+// d^8, truncation below 1e-19 relative for |d| < 1/32).
+__device__ inline void expm1_parts(double d, double &em1_minus_d, double &em1)
+{
+    if (fabs(d) < 0.03125) {
+        const double p = d * d *
+                         (0.5 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 + d * (1.0 / 5040 +
+                                                                                               d * (1.0 / 40320)))))));
+        em1_minus_d = p;
+        em1 = p + d;
+    } else {
+        em1 = expm1(d);
+        em1_minus_d = em1 - d;
+    }
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) divergence_kernel(const double *__restrict__ kappa,
+                                                         const double *__restrict__ cvals, uint32_t nc,
+                                                         double *__restrict__ D, double *__restrict__ dE)
+{
+    __shared__ DivNode nodes[kDivNodes];
+    const uint32_t i = blockIdx.y;
+    const KappaConst s = kappa_const(kappa[i]);
+    if (s.ok) {
+        const double lnk = log(s.kappa);
+        for (int n = threadIdx.x; n < kDivNodes; n += blockDim.x) {
+            const double t = (n - kDivNeg) * kDivH;
+            const double ell = kHalfPi * sinh(t);
+            const double x = exp(ell);
+            // eq:kappax in logs
+            const double lnf = -lnk - s.lnB + 0.5 * (ell - lnk) - (s.kappa + 1.0) * log1p(x / s.kappa);
+            const double wf = kDivH * kHalfPi * cosh(t) * x * exp(lnf);  // h dx/dt f(x)
+            nodes[n] = DivNode{x, exp(-ell), lnf, wf, wf * x};
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    const uint32_t j0 = blockIdx.x * kDivCPerBlock;
+    const uint32_t j1 = j0 + kDivCPerBlock < nc ? j0 + kDivCPerBlock : nc;
+    const double kstar = s.kstar, inv_kstar = 1.0 / s.kstar;
+    for (uint32_t j = j0 + wave; j < j1; j += nwaves) {
+        const double c = cvals ? cvals[j] : (s.ok ? c_from_eq_c(s.kappa) : 0.0);
+        double dsum = 0.0, esum = 0.0;
+        const bool ok = s.ok && isfinite(c) && c >= 0.0;
+        if (ok) {
+            const double a = s.a, b = s.b_over_c * c;
+            for (int n = lane; n < kDivNodes; n += 64) {
+                const DivNode nd = nodes[n];
+                const double inv = 1.0 / (1.0 + c * nd.x);
+                const double t1 = nd.x * inv;                      // x / (1 + c x) <= 1/c
+                const double y = (a + b * nd.x) * t1;
+                const double sl = log1p(y * inv_kstar);
+                const double ln1mE = log(-expm1(-kstar * sl));
+                const double yp = (a * nd.q + 2.0 * b + b * c * nd.x) * t1 * inv;
+                const double lng = 0.40546510810816438 + 0.5 * ln1mE - (kstar + 1.0) * sl + log(yp);  // ln(3/2) + ...
+                double em1_minus_d, em1;
+                expm1_parts(lng - nd.lnf, em1_minus_d, em1);
+                dsum += nd.w_d * em1_minus_d;
+                esum += nd.w_e * em1;
+            }
+        }
+        dsum = wave_sum(dsum);
+        esum = wave_sum(esum);
+        if (lane == 0) {
+            const size_t o = static_cast<size_t>(i) * nc + j;
+            const double nan = __builtin_nan("");
+            D[o] = ok ? dsum : nan;
+            if (dE) dE[o] = ok ? esum * (2.0 * s.kappa - 3.0) / (3.0 * s.kappa) : nan;
+        }
+    }
+}
+
+// One wave per kappa row: the index of the smallest D (NaN skipped, lowest
+// index on ties; 0xFFFFFFFF when the row has no number).
+__global__ void __launch_bounds__(64) argmin_kernel(const double *__restrict__ D, uint32_t nc,
+                                                    uint32_t *__restrict__ argmin)
+{
+    const uint32_t i = blockIdx.x;
+    const double *row = D + static_cast<size_t>(i) * nc;
+    double best = __builtin_inf();
+    uint32_t bj = 0xFFFFFFFFu;
+    for (uint32_t j = threadIdx.x; j < nc; j += 64) {
+        const double v = row[j];
+        if (v < best) {  // false for NaN; strict, so the lowest j of this lane wins ties
+            best = v;
+            bj = j;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(best, off, 64);
+        const uint32_t oj = __shfl_xor(bj, off, 64);
+        if (ov < best || (ov == best && oj < bj)) {
+            best = ov;
+            bj = oj;
+        }
+    }
+    if (threadIdx.x == 0) argmin[i] = bj;
+}
+
+}  // namespace
+
+hipError_t launch_divergence(const double *kappa, uint32_t nk, const double *c, uint32_t nc, double *D, double *dE,
+                             uint32_t *argmin, hipStream_t stream)
+{
+    const uint32_t per_block = nc < kDivCPerBlock ? nc : kDivCPerBlock;
+    const int waves = per_block < 4 ? static_cast<int>(per_block) : 4;
+    const dim3 grid((nc + kDivCPerBlock - 1) / kDivCPerBlock, nk);
+    hipLaunchKernelGGL(divergence_kernel, grid, dim3(64 * waves), 0, stream, kappa, c, nc, D, dE);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || !argmin) return err;
+    hipLaunchKernelGGL(argmin_kernel, dim3(nk), dim3(64), 0, stream, D, nc, argmin);
+    return hipGetLastError();
+}
+
+}  // namespace kappa

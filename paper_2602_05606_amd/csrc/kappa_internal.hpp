@@ -74,4 +74,13 @@ struct ExactArgs {
 hipError_t launch_exact_t(int mode, const ExactArgs &args, hipStream_t stream);
 hipError_t launch_exact_pareto(int mode, const ExactArgs &args, hipStream_t stream);
 
+// ---- speed histogram -------------------------------------------------------
+size_t histogram_lds_bytes(int mode, uint32_t nbins);
+hipError_t launch_histogram(int mode, const void *vx, const void *vy, const void *vz, uint64_t n, double width,
+                            uint32_t nbins, uint64_t *counts, hipStream_t stream);
+
+// ---- approximation quality over (kappa, c) ---------------------------------
+hipError_t launch_divergence(const double *kappa, uint32_t nk, const double *c, uint32_t nc, double *D, double *dE,
+                             uint32_t *argmin, hipStream_t stream);
+
 }  // namespace kappa

@@ -132,6 +132,23 @@ def test_exact_and_probe_argument_checks():
     assert lib.kappa_philox(0, 0, 0, 0, 0, None, None) == _lib.OK
 
 
+def test_histogram_and_divergence_argument_checks():
+    lib = _lib.load()
+    assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, 1.0, 0.2, 0, FAKE, None) == _lib.ERANGE
+    assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, 1.0, 0.2, 2048, FAKE, None) == _lib.ERANGE
+    assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, -1.0, 0.2, 10, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, 1.0, 0.2, 10, ctypes.c_void_p(0x10004), None) == _lib.EALIGN
+    assert lib.kappa_speed_histogram(None, None, None, 0, 1, 1.0, 0.2, 10, FAKE, None) == _lib.OK
+    div = lib.kappa_divergence_grid
+    assert div(FAKE, 65536, FAKE, 1, FAKE, None, None, None) == _lib.ERANGE
+    assert div(FAKE, 4, FAKE, (1 << 24) + 1, FAKE, None, None, None) == _lib.ERANGE
+    assert div(FAKE, 4, None, 2, FAKE, None, None, None) == _lib.EINVAL     # eq:c column needs nc = 1
+    assert div(None, 4, FAKE, 2, FAKE, None, None, None) == _lib.EINVAL
+    assert div(FAKE, 4, FAKE, 2, ctypes.c_void_p(0x10004), None, None, None) == _lib.EALIGN
+    assert div(FAKE, 4, FAKE, 2, FAKE, None, ctypes.c_void_p(0x10002), None) == _lib.EALIGN
+    assert div(None, 0, None, 0, None, None, None, None) == _lib.OK
+
+
 def test_segment_struct_layout():
     assert ctypes.sizeof(_lib.Segment) == 56
 

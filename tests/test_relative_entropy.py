@@ -1,0 +1,103 @@
+"""CPU pins of the Monte Carlo relative-entropy validator (Sec. 5, second test).
+
+* The oracle's speed histogram against inputs constructed on its bin edges
+  (brute force on tiny inputs) and against the definition evaluated with
+  numpy's IEEE float arithmetic on random data.
+* relative_entropy (eq:KL) of the exact bin probabilities of the
+  approximation G against the exact Kappa bins equals the continuous relative
+  entropy of eq:relative_entropy by quadrature, as the paper says D ~ calD.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import paper_2602_05606_amd as kp
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_histogram_on_constructed_edges(orc, dtype):
+    # theta = 1, w = 1/4: the edges k/4 and their squares are exact in both precisions
+    nbins = 40
+    ks = np.arange(0, nbins + 3)
+    vals = (ks / 4.0).astype(dtype)
+    below = np.nextafter(vals, dtype(0)).astype(dtype)
+    vx = np.concatenate([vals, below[1:]])
+    zero = np.zeros_like(vx)
+    counts = orc.speed_histogram(vx, zero, zero, 1.0, 0.25, nbins)
+    expect = np.zeros(nbins + 1, dtype=np.uint64)
+    for k in ks:
+        expect[min(k, nbins)] += 1            # exactly on edge k -> bin k
+    for k in ks[1:]:
+        expect[min(k - 1, nbins)] += 1        # just below edge k -> bin k-1
+    np.testing.assert_array_equal(counts, expect)
+    # the speed is |v|: the same value spread over three components lands in the same bin
+    third = (vals / math.sqrt(3)).astype(dtype)
+    c3 = orc.speed_histogram(third, third, third, 1.0, 0.25, nbins)
+    assert c3.sum() == len(ks)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_histogram_matches_its_definition(orc, dtype):
+    rng = np.random.default_rng(5)
+    v = (rng.standard_normal((3, 200_000)) * 1.7).astype(dtype)
+    theta, w, nbins = 1.3, 0.2, 60
+    counts = orc.speed_histogram(v[0], v[1], v[2], theta, w, nbins)
+    s2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]
+    edges2 = ((np.arange(nbins + 1) * (w * theta)) ** 2).astype(dtype)
+    idx = np.searchsorted(edges2, s2, side="right") - 1
+    ref = np.bincount(np.minimum(idx, nbins), minlength=nbins + 1).astype(np.uint64)
+    np.testing.assert_array_equal(counts, ref)
+    # accumulation
+    again = orc.speed_histogram(v[0], v[1], v[2], theta, w, nbins, counts=counts.copy())
+    np.testing.assert_array_equal(again, 2 * ref)
+
+
+def _continuous_relative_entropy(orc, k):
+    lnB = special.betaln(1.5, k - 0.5)
+
+    def f(x):
+        return math.exp(-math.log(k) - lnB + 0.5 * math.log(x / k) - (k + 1) * math.log1p(x / k))
+
+    def integrand(x):
+        return f(x) * math.log(f(x) / orc.g_pdf(k, x)) if x > 0 else 0.0
+
+    edges = [0, 1e-6, 1e-3, 0.1, 1, 3, 10, 30, 100, 1e3, 1e4, 1e5, 1e6, 1e8, 1e10, np.inf]
+    return sum(integrate.quad(integrand, a, b, limit=400, epsabs=1e-16, epsrel=1e-10)[0]
+               for a, b in zip(edges[:-1], edges[1:]))
+
+
+@pytest.mark.parametrize("kappa", [3.0, 4.1, 7.5])
+def test_binned_relative_entropy_of_G_equals_the_continuous_one(orc, kappa):
+    w, nbins = 0.2, 100
+    edges = np.arange(nbins + 1) * w
+    G = np.array([orc.G(kappa, e * e)[0] for e in edges])
+    q = np.append(np.diff(G), orc.G(kappa, edges[-1] ** 2)[1])
+    D = kp.relative_entropy(kappa, q * 1e18, w)
+    cal = _continuous_relative_entropy(orc, kappa)
+    assert abs(D / cal - 1) < 0.05, (D, cal)
+
+
+def test_relative_entropy_of_the_exact_bins_is_zero():
+    from scipy import special as sp
+    kappa, w, nb = 3.0, 0.2, 100
+    x = (np.arange(nb + 1) * w) ** 2
+    cdf = sp.betainc(1.5, kappa - 0.5, x / (x + kappa))
+    p = np.append(np.diff(cdf), 1 - cdf[-1])
+    assert abs(kp.relative_entropy(kappa, p * 1e18, w)) < 1e-12
+    # any other distribution scores higher
+    assert kp.relative_entropy(kappa, np.roll(p, 1) * 1e18, w) > 1e-3
+
+
+def test_relative_entropy_of_exact_samples_scales_as_one_over_n(orc):
+    """For exact sampling E[D] ~ (B - 1)/(2N) over the B occupied bins; the
+    oracle's samples at kappa = 3 (sup|G - F| far below the noise) follow it."""
+    kappa, w, nb = 3.0, 0.2, 100
+    n = 2_000_000
+    vx, vy, vz, _ = orc.sample(kappa, 1.0, n, 41)
+    counts = orc.speed_histogram(vx, vy, vz, 1.0, w, nb)
+    D = kp.relative_entropy(kappa, counts, w)
+    occupied = int(np.count_nonzero(counts))
+    expect = (occupied - 1) / (2 * n)
+    assert 0.5 * expect < D < 2.0 * expect, (D, expect)
