@@ -16,6 +16,7 @@ backward and batched forms, and the CPU oracle as a baseline.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -173,6 +174,57 @@ def relative_entropy_test2(kp, torch, dev, kappas=(3.0, 4.1, 7.5), n_max=10 ** 1
     return res
 
 
+def mt_acceptance(kappa):
+    """eq:mt_eff: acceptance of the Marsaglia-Tsang gamma rejection at shape
+    k = kappa - 1/2 (the loop inside the t-form exact generator)."""
+    k = kappa - 0.5
+    return math.exp(k - 1.0 / 3 + math.lgamma(k) - 0.5 * math.log(2 * math.pi) - (k - 0.5) * math.log(k - 1.0 / 3))
+
+
+def pareto_acceptance(kappa):
+    """eq:pareto_eff: acceptance of the Type II Pareto rejection with index kappa/2."""
+    ln_b = math.lgamma(1.5) + math.lgamma(kappa - 0.5) - math.lgamma(kappa + 1)
+    return math.exp((1 + kappa / 2) * math.log(kappa) - math.log(2) - 0.5 * (kappa - 1) * math.log(kappa - 1) + ln_b)
+
+
+def ridley_mu1(rho, t):
+    """eq:ridley1: typical loop count of t lanes in lock step, rejection rate rho
+    below about 2^(1/t) - 1."""
+    return 3 - (1 - rho) ** t - (1 - rho * rho) ** t
+
+
+def ridley_mu2(rho, t):
+    """eq:ridley2: the same for rho well above 2^(1/t) - 1."""
+    return math.log(2 * (rho - 1) * t / math.log(rho)) / math.log(1 / rho) + 1
+
+
+def simt_loop_counts(kp, torch, kappas, theta, seed, n=1 << 24):
+    """Sec. 6's SIMT cost model against the GPU: for each kappa, the per-particle
+    loop counts of the two exact generators (mean ~ 1/p), the mean over groups
+    of t consecutive particles of their largest count (the count a t-wide SIMT
+    group waits for: t = 64 is the MI355X wave, t = 32 the paper's warp), and
+    the model's mu1 (t-gamma) and mu2 (Pareto) with the variates per particle
+    it predicts, 3 + 2 mu1 and 2 + 2 mu2."""
+    res = {"n": n, "threshold_2^(1/t)-1": {"32": 2 ** (1 / 32) - 1, "64": 2 ** (1 / 64) - 1}}
+    for k in kappas:
+        row = {}
+        for name, fn, p in (("t_gamma", kp.sample_exact_t, mt_acceptance(k)),
+                            ("pareto", kp.sample_exact_pareto, pareto_acceptance(k))):
+            *_, it = fn(k, theta, n, seed, precision=kp.FP32, with_iters=True)
+            it = it.to(torch.float64)
+            entry = {"acceptance": p, "mean_loops": it.mean().item(), "cpu_variates_model": (3 + 2 / p)
+                     if name == "t_gamma" else (2 + 2 / p)}
+            for t in (32, 64):
+                rho = 1 - p
+                mu = ridley_mu1(rho, t) if name == "t_gamma" else ridley_mu2(rho, t)
+                entry[f"group_max_mean_t{t}"] = it.view(-1, t).max(dim=1).values.mean().item()
+                entry[f"model_mu_t{t}"] = mu
+                entry[f"model_variates_t{t}"] = (3 + 2 * mu) if name == "t_gamma" else (2 + 2 * mu)
+            row[name] = entry
+        res[str(k)] = row
+    return res
+
+
 def divergence_survey(kp, torch, dev):
     """The grid search behind eq:c (Sec. 3, Fig. fig:map): D(f||g; kappa, c) on
     c in [0, 1.5] x kappa in (1.5, 10] at steps 0.005 and 0.01, with the
@@ -226,17 +278,29 @@ def cpu_baseline(seconds_target=15.0):
                       f"FP64 arithmetic), {dt:.1f} s on the host"}
 
 
+EXTRAS = ("rates", "simt", "ks", "test2", "survey", "c5", "fp64", "backward", "batched")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="same as --extras none")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extra measurements to run after the timed steps, 'all' or 'none': "
+                         + ",".join(EXTRAS))
     ap.add_argument("--calibrate", action="store_true",
                     help="also run the plain copy probe on 1.2e9 bytes (3 launches) and the store probe, so that "
                          "rocprofv3 counters can be scaled against known traffic")
     args = ap.parse_args()
+    chosen = set(EXTRAS) if args.extras == "all" else set() if args.extras == "none" else set(args.extras.split(","))
+    if args.no_extras:
+        chosen = set()
+    unknown = chosen - set(EXTRAS)
+    if unknown:
+        ap.error(f"unknown extras {sorted(unknown)}; choose from {','.join(EXTRAS)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the generator needs no communication, and a run on N GPUs is "
               "N independent counter ranges (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
@@ -310,8 +374,8 @@ def main():
         log("calibration copies done (copy_kernel: 1.2e9 bytes read and written per launch; "
             "fill_kernel: 1.2e9 bytes written per launch)")
 
-    if not args.no_extras:
-        extras = {}
+    extras = {}
+    if "rates" in chosen:
         per_kappa = {}
         for k in kappas:
             ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
@@ -333,12 +397,19 @@ def main():
                              "approx_speedup_vs_pareto": per_kappa[str(k)] / rate_p}
         extras["exact_generators_fp32_particles_per_s"] = exact
         log("exact generators done")
+    if "simt" in chosen:
+        extras["simt_rejection_loops"] = simt_loop_counts(kp, torch, kappas, theta, seed)
+        log("SIMT loop counts done")
+    if "ks" in chosen:
         extras["ks_vs_exact_cdf"] = ks_table(kp, torch, kappas, theta, seed, out32)
         log("KS distances done")
+    if "test2" in chosen:
         extras["relative_entropy_test2"] = relative_entropy_test2(kp, torch, dev)
         log("relative-entropy test done")
+    if "survey" in chosen:
         extras["divergence_survey"] = divergence_survey(kp, torch, dev)
         log("divergence survey done")
+    if "c5" in chosen:
         c5 = workloads.C5
         chunk_out = tuple(t[:c5["chunk"]] for t in out32) if c5["chunk"] <= n else None
         if chunk_out is None:
@@ -353,7 +424,8 @@ def main():
         extras["c5_stream_fp32"] = {"particles": c5["n"], "chunks": len(workloads.c5_chunks()), "s": dt5,
                                     "particles_per_s": c5["n"] / dt5}
         del chunk_out
-        del out32
+    del out32
+    if "fp64" in chosen:
         out64 = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
         fp64 = {}
         for k in kappas:
@@ -364,6 +436,7 @@ def main():
         extras["store_probe_fp64_GB_per_s"] = 24 * n / (fill64 * 1e-3) / 1e9
         del out64
         log("FP64 sweep done")
+    if "backward" in chosen:
         c3 = workloads.C3
         gen = torch.Generator(device=dev).manual_seed(c3["grad_seed"])
         g = torch.randn((3, c3["n"]), generator=gen, device=dev, dtype=torch.float32)
@@ -374,6 +447,7 @@ def main():
                                  "GB_per_s_read": 12 * c3["n"] / (bw_ms * 1e-3) / 1e9}
         del g
         log("backward done")
+    if "batched" in chosen:
         segs = workloads.batched_segments()
         with kp.Plan(segs, workloads.C4["seed"], kp.FP32) as plan:
             outb = plan.outputs()
@@ -397,6 +471,7 @@ def main():
                                     "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),
                                     "single_species_same_size_ms": single_ms}
         log("batched done")
+    if extras:
         result["extras"] = extras
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()

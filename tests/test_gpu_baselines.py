@@ -64,3 +64,22 @@ def test_exact_generators(which, kappa, precision):
     assert p > 1e-4 and pc > 1e-4
     assert it.min() >= 1 and it.max() < 64
     assert abs(mean_it - 1 / acc) < 6 * sd
+
+
+@pytest.mark.parametrize("which", ["t", "pareto"])
+def test_wave_loop_counts_follow_the_geometric_model(which):
+    """Sec. 6: a SIMT group waits for its slowest lane.  With independent
+    Philox draws per iteration the loop counts are geometric with rejection
+    rate rho = 1 - p, so the largest of t of them has mean
+    sum_k 1 - (1 - rho^k)^t; checked for t = 64 (the wave) and 32."""
+    kappa, n = 3.0, 1 << 22
+    fn = kp.sample_exact_t if which == "t" else kp.sample_exact_pareto
+    *_, it = fn(kappa, 1.0, n, 23, precision=kp.FP32, with_iters=True)
+    it = it.to(torch.float64)
+    rho = 1 - (p1(kappa - 0.5) if which == "t" else p2(kappa))
+    k = np.arange(0, 400)
+    for t in (32, 64):
+        expect = float(np.sum(1 - (1 - rho ** k) ** t))
+        got = it.view(-1, t).max(dim=1).values.mean().item()
+        print(f"{which} t={t}: mean of group max {got:.4f}, geometric model {expect:.4f}")
+        assert abs(got - expect) < 0.03
