@@ -381,6 +381,8 @@ def main():
             ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
             per_kappa[str(k)] = n / (ms * 1e-3)
         extras["fp32_per_kappa_particles_per_s"] = per_kappa
+        ms = time_launches(lambda: kp.sample(math.inf, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
+        extras["maxwell_limit_fp32_particles_per_s"] = n / (ms * 1e-3)
         fill_ms = time_launches(lambda: kp.fill_probe(n, kp.FP32, out32), 5, torch)
         extras["store_probe_fp32"] = {"GB_per_s": 12 * n / (fill_ms * 1e-3) / 1e9,
                                       "particles_per_s": n / (fill_ms * 1e-3)}
@@ -466,10 +468,21 @@ def main():
             # the single-species kernel on the same number of particles, for comparison
             single_ms = time_launches(lambda: kp.sample(3.0, 1.0, plan.total, 4, precision=kp.FP32, out=outb), 20,
                                       torch)
+            # fused particle loading: positions in each cell's box with the velocities
+            plan.set_cells(workloads.batched_cells())
+            posb = plan.outputs()
+            plan.launch_pic(posb, outb)
+            pic_ms = time_launches(lambda: plan.launch_pic(posb, outb), 20, torch)
+            plan.graph_launch_pic(posb, outb)
+            pic_graph_ms = time_launches(lambda: plan.graph_launch_pic(posb, outb), 20, torch)
             extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
                                     "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
                                     "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),
-                                    "single_species_same_size_ms": single_ms}
+                                    "single_species_same_size_ms": single_ms,
+                                    "pic_positions_and_velocities": {
+                                        "direct_launch_ms": pic_ms, "graph_launch_ms": pic_graph_ms,
+                                        "particles_per_s": plan.total / (pic_ms * 1e-3),
+                                        "GB_per_s_written": 24 * plan.total / (pic_ms * 1e-3) / 1e9}}
         log("batched done")
     if extras:
         result["extras"] = extras

@@ -96,13 +96,20 @@ enum {
  * the host: kappa*, a, c, b per eq:k2, eq:a, eq:c, eq:b, with
  * B(3/2, kappa*) = Gamma(3/2) Gamma(kappa*) / Gamma(kappa + 1) (Sec. 6), and
  * their kappa-derivatives.  out: host array of KAPPA_NPARAMS doubles, indexed
- * by KAPPA_P_*.  No HIP call.  KAPPA_EINVAL for a bad kappa or NULL out. */
+ * by KAPPA_P_*.  No HIP call.  KAPPA_EINVAL for a bad kappa or NULL out.
+ * kappa = +INFINITY is the Maxwell limit (accepted wherever the sampler takes
+ * kappa): exp_q* -> exp and the q-logarithm of eq:L -> ln; a and b/c take
+ * the kappa -> inf limits of Sec. 3, (4/(3 sqrt(pi)))^(2/3) and 1; c is 0.079,
+ * the three-figure minimiser of the relative entropy of eq:relative_entropy
+ * against the Maxwell density (the paper's criterion for c; it gives no
+ * Maxwell constants).  kappa* is reported as +inf and the derivatives as 0. */
 KAPPA_API kappa_status kappa_params(double kappa, double *out);
 
 /* kappa_sample -- one species: particles counter_offset .. counter_offset+n-1
  * of segment seg_id, Table 1 per particle (Sec. 4).  vx, vy, vz: device arrays
  * of n elements (see conventions).  n = 0 is a no-op returning KAPPA_OK.
- * counter_offset + n must not exceed 2^64 (KAPPA_EINVAL). */
+ * counter_offset + n must not exceed 2^64 (KAPPA_EINVAL).  kappa > 3/2, or
+ * +INFINITY for the Maxwell limit (see kappa_params). */
 KAPPA_API kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed,
                           uint64_t counter_offset, uint32_t seg_id, int precision,
                           void *vx, void *vy, void *vz, void *stream);
@@ -119,6 +126,14 @@ typedef struct {
     uint32_t seg_id;
     uint32_t reserved; /* must be 0 */
 } kappa_segment;
+
+/* A cell box for fused particle loading: positions of a segment's particles
+ * are drawn uniformly in [lo, lo + size) per axis.  Not in the paper, which
+ * samples velocities only; a PIC code loads both at start-up. */
+typedef struct {
+    double lo[3];   /* lower corner, finite */
+    double size[3]; /* edge lengths, finite and >= 0 */
+} kappa_cell;
 
 /* Opaque batched plan: device copies of the segment table and of the tile ->
  * segment map, the chosen launch shape, and a captured hipGraph. */
@@ -165,6 +180,28 @@ KAPPA_API kappa_status kappa_plan_shape(kappa_plan plan, int *block, int *unroll
 KAPPA_API kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int grid);
 
 /* Release the plan's device memory and graph.  NULL is a no-op. */
+/* kappa_plan_set_cells -- give the plan one cell box per segment (host array
+ * of the plan's nseg cells, in segment order; copied to a plan-owned device
+ * table, so the host array may be freed).  NULL removes the table.  Replacing
+ * a table synchronises the device.  KAPPA_EINVAL for a non-finite lo or a
+ * size that is negative or not finite. */
+KAPPA_API kappa_status kappa_plan_set_cells(kappa_plan plan, const kappa_cell *cells);
+
+/* kappa_plan_launch_pic / kappa_plan_graph_launch_pic -- fused particle
+ * loading: the plan's launch (direct, or through its captured hipGraph) that
+ * also writes positions px, py, pz (device arrays of kappa_plan_total
+ * elements, same type as the velocities).  Particle j of a segment is placed
+ * at lo + u size, with u from the Philox block of draw 1 of its counter
+ * (velocities use draw 0 and are bit-identical to kappa_plan_launch):
+ * u = (r + 1/2) 2^-32 in KAPPA_FP64, (floor(r / 2^9) + 1/2) 2^-23 in the
+ * FP32 modes, for r = r0, r1, r2 on x, y, z; one fused multiply-add in the
+ * output precision.  KAPPA_EINVAL without kappa_plan_set_cells.
+ * Asynchronous. */
+KAPPA_API kappa_status kappa_plan_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx, void *vy,
+                                             void *vz, void *stream);
+KAPPA_API kappa_status kappa_plan_graph_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx,
+                                                   void *vy, void *vz, void *stream);
+
 KAPPA_API kappa_status kappa_plan_destroy(kappa_plan plan);
 
 /* kappa_sample_batched -- many species and cells in one persistent launch:
@@ -178,7 +215,8 @@ KAPPA_API size_t kappa_backward_workspace_bytes(uint64_t n);
 
 /* kappa_sample_backward -- reparameterisation gradient of a loss through the
  * samples of kappa_sample (same kappa, theta, n, seed, counter_offset,
- * seg_id, precision), at fixed uniforms.  Not in the paper; it differentiates
+ * seg_id, precision), at fixed uniforms; finite kappa only (KAPPA_EINVAL for
+ * +INFINITY).  Not in the paper; it differentiates
  * Table 1: dv/dtheta = v/theta, and dv/dkappa = v (dx/dkappa) / (2x), where
  * x = (V/theta)^2 solves b x^2 + (a + cL) x + L = 0 (eq:v, eq:L), so
  * dx/dkappa = -(b' x^2 + (a' + c' L + c L') x + L') / sqrt((a+cL)^2 - 4bL).
@@ -195,6 +233,13 @@ KAPPA_API kappa_status kappa_sample_backward(double kappa, double theta, uint64_
                                    const void *gx, const void *gy, const void *gz, double *grad,
                                    void *workspace, size_t workspace_bytes, void *stream);
 
+/* kappa_load_particles -- one-shot fused particle loading: kappa_plan_create,
+ * kappa_plan_set_cells and kappa_plan_launch_pic, then waits for the stream
+ * and frees the plan.  cells: host array of nseg boxes. */
+KAPPA_API kappa_status kappa_load_particles(const kappa_segment *segs, const kappa_cell *cells, uint32_t nseg,
+                                            uint64_t seed, int precision, void *px, void *py, void *pz, void *vx,
+                                            void *vy, void *vz, void *stream);
+
 /* kappa_philox -- raw Philox4x32-10 blocks for particles counter_offset ..
  * counter_offset+n-1 of segment seg_id and draw number draw: out is a device
  * array of 4n uint32 words (r0, r1, r2, r3 per particle).  For bit-exact
@@ -205,7 +250,7 @@ KAPPA_API kappa_status kappa_philox(uint64_t n, uint64_t seed, uint64_t counter_
 /* Same-GPU exact Kappa generators used as performance comparators (Sec. 5,
  * third test; Sec. 6).  Both sample the exact distribution of eq:kappa with
  * rejection loops on the same Philox stream: iteration t of particle i uses
- * the block with counter (i, 0, t).  precision KAPPA_FP64 (double outputs) or
+ * the block with counter (i, 0, t).  Finite kappa > 3/2 only.  precision KAPPA_FP64 (double outputs) or
  * KAPPA_FP32 (float outputs, FP32 arithmetic).  iters: optional device array
  * of n uint32 (NULL to skip) receiving the number of rejection-loop
  * iterations each particle took.
@@ -249,11 +294,13 @@ KAPPA_API kappa_status kappa_speed_histogram(const void *vx, const void *vy, con
  * definitions the rule is within 1e-12 relative for D and 1e-14 absolute for
  * dE (for c = 0 the energy tail decays like x^(1/2 - kappa), so dE is only
  * settled for kappa >= 1.6 there).
- *   kappa   device array of nk doubles.  Entries that are not finite or not
- *           above 3/2 give NaN rows.
+ *   kappa   device array of nk doubles.  Entries that are NaN or not above
+ *           3/2 give NaN rows.  +INFINITY is the Maxwell limit: f is then the
+ *           Maxwell density 2/sqrt(pi) x^(1/2) e^-x, exp_q* -> exp, a and b/c
+ *           at their limits (see kappa_params), E_kappa = 3/2.
  *   c       device array of nc doubles (c >= 0; other entries give NaN), or
- *           NULL with nc = 1 to take c from eq:c for each kappa (the paper's
- *           curve of Fig. fig:DE).
+ *           NULL with nc = 1 to take the c the sampler uses: eq:c for each
+ *           kappa (the paper's curve of Fig. fig:DE), 0.079 for +INFINITY.
  *   D       device array of nk*nc doubles, written (row i = kappa_i).
  *   dE      device array of nk*nc doubles, written; NULL to skip.
  *   argmin  device array of nk uint32, written with the j of the smallest
@@ -261,6 +308,7 @@ KAPPA_API kappa_status kappa_speed_histogram(const void *vx, const void *vy, con
  *           NULL to skip.
  * nk <= 65535 and nc <= 2^24 (else KAPPA_ERANGE); 8-byte aligned doubles,
  * 4-byte aligned argmin (else KAPPA_EALIGN).  nk = 0 or nc = 0 is a no-op.
+ * Nodes where f has underflowed to zero are skipped.
  * Asynchronous. */
 KAPPA_API kappa_status kappa_divergence_grid(const double *kappa, uint32_t nk, const double *c, uint32_t nc,
                                              double *D, double *dE, uint32_t *argmin, void *stream);

@@ -59,6 +59,8 @@ def _load():
     lib.oracle_sample.restype = c_u64
     lib.oracle_sample_indices.argtypes = [c_d, c_d, dp, u64p, c_u64, c_u64, c_u32, c_int, dp, dp, dp]
     lib.oracle_sample_indices.restype = None
+    lib.oracle_positions.argtypes = [dp, dp, c_u64, c_u64, c_u64, c_u32, c_int, dp, dp, dp]
+    lib.oracle_positions.restype = None
     lib.oracle_backward.argtypes = [c_d, c_d, c_u64, c_u64, c_u64, c_u32, c_int, fp, fp, fp, dp]
     lib.oracle_backward.restype = None
     lib.oracle_find_tails.argtypes = [c_u64, c_u64, c_u64, c_u32, u64p, c_u64]
@@ -146,6 +148,18 @@ def sample(kappa, theta, n, seed, counter_offset=0, seg=0, mode=MODE_FP64, drift
     tails = lib.oracle_sample(float(kappa), float(theta), dptr, n, seed, counter_offset, seg, mode,
                               _ptr(vx, ctypes.c_double), _ptr(vy, ctypes.c_double), _ptr(vz, ctypes.c_double))
     return vx, vy, vz, int(tails)
+
+
+def positions(lo, size, n, seed, counter_offset=0, seg=0, mode=MODE_FP64):
+    """(px, py, pz): particles counter_offset..+n-1 of segment seg placed
+    uniformly in the box [lo, lo + size) (draw 1 of the counter)."""
+    lib = _load()
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    size = np.ascontiguousarray(size, dtype=np.float64)
+    out = [np.empty(n, dtype=np.float64) for _ in range(3)]
+    lib.oracle_positions(_ptr(lo, ctypes.c_double), _ptr(size, ctypes.c_double), n, seed, counter_offset, seg,
+                         mode, *(_ptr(a, ctypes.c_double) for a in out))
+    return tuple(out)
 
 
 def sample_indices(kappa, theta, idx, seed, seg=0, mode=MODE_FP64, drift=None):

@@ -115,8 +115,27 @@ enum {
     OP_KSTAR = 0, OP_A, OP_B, OP_C, OP_B_OVER_C, OP_DA, OP_DB, OP_DC, OP_LNBETA, OP_COUNT
 };
 
+/* The Maxwell limit, kappa = +inf (a variant on the same construction; the
+ * paper gives no constants for it): q* -> 1, so exp_q* -> exp in eq:G and
+ * the q-logarithm of eq:L -> ln; a and b/c take the limits Sec. 3 states,
+ * a = (4 / (3 sqrt(pi)))^(2/3) and b/c = 1; c is the value that minimises
+ * the relative entropy of eq:relative_entropy with the Maxwell density
+ * 2/sqrt(pi) x^(1/2) e^-x in place of eq:kappax (0.078998 by a 30-digit
+ * quadrature), rounded to three figures as eq:c's constants are. */
+#define ORACLE_C_MAXWELL 0.079
+
 void oracle_params(double kappa, double *p)
 {
+    if (isinf(kappa) && kappa > 0) {
+        p[OP_KSTAR] = INFINITY;
+        p[OP_A] = pow(4.0 / (3.0 * sqrt(M_PI)), 2.0 / 3.0);
+        p[OP_C] = ORACLE_C_MAXWELL;
+        p[OP_B_OVER_C] = 1.0;
+        p[OP_B] = ORACLE_C_MAXWELL;
+        p[OP_DA] = p[OP_DB] = p[OP_DC] = 0.0;
+        p[OP_LNBETA] = -INFINITY;
+        return;
+    }
     double ks = kappa - 0.5;
     double lnB = lgamma(1.5) + lgamma(ks) - lgamma(kappa + 1.0);
     double a = (1.0 / kappa) * pow(2.0 / (3.0 * exp(lnB)), 2.0 / 3.0);
@@ -222,7 +241,7 @@ static void invert(const double *p, int side, double u, inversion *r)
         lT = log(-expm1((2.0 / 3.0) * lnU1));  /* ln(1 - U1^(2/3)) */
     }
     double z = -lT / ks;
-    double L = -ks * expm1(z);
+    double L = isinf(ks) ? lT : -ks * expm1(z);  /* ln_q -> ln as q* -> 1 */
     double A = a + c * L;
     double D = sqrt(A * A - 4.0 * b * L);
     double x = (A >= 0.0) ? (-2.0 * L) / (A + D) : (D - A) / (2.0 * b);
@@ -248,7 +267,7 @@ void oracle_G(double kappa, double x, double *G, double *one_minus_G)
     oracle_params(kappa, p);
     double ks = p[OP_KSTAR], a = p[OP_A], b = p[OP_B], c = p[OP_C];
     double w = (a * x + b * x * x) / (1.0 + c * x);
-    double ln_e = -ks * log1p(w / ks);       /* ln exp_{q*}(-w) */
+    double ln_e = isinf(ks) ? -w : -ks * log1p(w / ks);  /* ln exp_{q*}(-w) */
     double inner = -expm1(ln_e);             /* 1 - exp_{q*}(-w) */
     *G = exp(1.5 * log(inner));
     *one_minus_G = -expm1(1.5 * log1p(-exp(ln_e)));
@@ -260,8 +279,12 @@ double oracle_g_pdf(double kappa, double x)
     double p[OP_COUNT];
     oracle_params(kappa, p);
     double ks = p[OP_KSTAR], a = p[OP_A], b = p[OP_B], c = p[OP_C];
-    double ratio = 1.0 + (a * x + b * x * x) / (ks * (1.0 + c * x));
     double pre = 3.0 * (a + 2.0 * b * x + b * c * x * x) / (2.0 * (1.0 + c * x) * (1.0 + c * x));
+    if (isinf(ks)) {
+        double w = (a * x + b * x * x) / (1.0 + c * x);
+        return pre * sqrt(-expm1(-w)) * exp(-w);
+    }
+    double ratio = 1.0 + (a * x + b * x * x) / (ks * (1.0 + c * x));
     return pre * sqrt(1.0 - pow(ratio, -ks)) * pow(ratio, -(ks + 1.0));
 }
 
@@ -310,6 +333,31 @@ uint64_t oracle_sample(double kappa, double theta, const double *drift, uint64_t
         vx[j] = v[0]; vy[j] = v[1]; vz[j] = v[2];
     }
     return tails;
+}
+
+/* Particle positions for fused particle loading (not in the paper, which
+ * samples velocities only): particle i of a segment takes the Philox block
+ * with counter (i, seg, draw 1) and sits at lo[k] + u_k size[k] on axis k,
+ * where u_k is the open midpoint dyadic of word r_k (k = 0, 1, 2):
+ * (r_k + 1/2) 2^-32 in FP64 mode and (floor(r_k / 2^9) + 1/2) 2^-23 in the
+ * FP32 modes (24 significant bits: exact in float, below 1).  FP64
+ * arithmetic. */
+void oracle_positions(const double *lo, const double *size, uint64_t n, uint64_t seed,
+                      uint64_t counter_offset, uint32_t seg, int mode, double *px, double *py,
+                      double *pz)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < (int64_t)n; ++j) {
+        uint32_t r[4];
+        double u[3];
+        particle_block(seed, counter_offset + (uint64_t)j, seg, 1, r);
+        for (int k = 0; k < 3; ++k)
+            u[k] = mode == MODE_FP64 ? ldexp((double)r[k] + 0.5, -32)
+                                     : ldexp((double)(r[k] >> 9) + 0.5, -23);
+        px[j] = lo[0] + u[0] * size[0];
+        py[j] = lo[1] + u[1] * size[1];
+        pz[j] = lo[2] + u[2] * size[2];
+    }
 }
 
 /* Same as oracle_sample, for an arbitrary list of particle indices. */

@@ -13,13 +13,13 @@ inversion when 1 - U1 < 2^-20) and FP32_NOTAIL (diagnostics).
 import ctypes
 
 from . import _lib
-from ._lib import FP32, FP32_NOTAIL, FP64, KappaError, Segment
+from ._lib import FP32, FP32_NOTAIL, FP64, Cell, KappaError, Segment
 
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
     "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
-    "relative_entropy",
+    "relative_entropy", "divergence_grid", "load_particles", "Cell",
 ]
 
 
@@ -207,6 +207,24 @@ class Plan:
         _lib.check(_lib.load().kappa_plan_graph_launch(self._h, _ptr(vx), _ptr(vy), _ptr(vz),
                                                        _stream(stream, vx.device)), "kappa_plan_graph_launch")
 
+    def set_cells(self, cells):
+        """One box per segment (in segment order) for fused particle loading:
+        an array-like of shape (nseg, 2, 3) holding (lo, size), or None to
+        remove the table (kappa_plan_set_cells)."""
+        c = None if cells is None else _cells(cells, len(self._segs))
+        _lib.check(_lib.load().kappa_plan_set_cells(self._h, c), "kappa_plan_set_cells")
+
+    def launch_pic(self, pos, vel, stream=None):
+        """Positions and velocities in one launch (kappa_plan_launch_pic)."""
+        _lib.check(_lib.load().kappa_plan_launch_pic(self._h, *(_ptr(t) for t in pos), *(_ptr(t) for t in vel),
+                                                     _stream(stream, vel[0].device)), "kappa_plan_launch_pic")
+
+    def graph_launch_pic(self, pos, vel, stream=None):
+        """launch_pic through the plan's captured hipGraph (kappa_plan_graph_launch_pic)."""
+        _lib.check(_lib.load().kappa_plan_graph_launch_pic(self._h, *(_ptr(t) for t in pos),
+                                                           *(_ptr(t) for t in vel), _stream(stream, vel[0].device)),
+                   "kappa_plan_graph_launch_pic")
+
     def autotune(self, out, reps=5, stream=None):
         vx, vy, vz = out
         _lib.check(_lib.load().kappa_plan_autotune(self._h, _ptr(vx), _ptr(vy), _ptr(vz), reps,
@@ -239,6 +257,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _cells(cells, nseg):
+    import numpy as np
+    arr = np.asarray(cells, dtype=np.float64).reshape(-1, 2, 3)
+    if arr.shape[0] != nseg:
+        raise ValueError(f"{arr.shape[0]} cells for {nseg} segments")
+    out = (_lib.Cell * nseg)()
+    for s in range(nseg):
+        out[s].lo[:] = arr[s, 0].tolist()
+        out[s].size[:] = arr[s, 1].tolist()
+    return out
+
+
+def load_particles(segments, cells, seed, precision=FP32, device=None, stream=None):
+    """One-shot fused particle loading (kappa_load_particles, synchronous):
+    returns ((px, py, pz), (vx, vy, vz)).  cells: (nseg, 2, 3) of (lo, size)."""
+    segs = _segments(segments)
+    total = sum(int(s.count) for s in segs)
+    pos = _outputs(total, precision, None, device)
+    vel = _outputs(total, precision, None, device)
+    st = _lib.load().kappa_load_particles(segs, _cells(cells, len(segs)), len(segs), seed, precision,
+                                          *(_ptr(t) for t in pos), *(_ptr(t) for t in vel),
+                                          _stream(stream, vel[0].device))
+    _lib.check(st, "kappa_load_particles")
+    return pos, vel
 
 
 def sample_batched(segments, seed, precision=FP32, out=None, device=None, stream=None):
@@ -327,17 +371,23 @@ def relative_entropy(kappa, counts, bin_width=0.2, eps=1e-10):
     exact Kappa probability of speed bin i (bins of width bin_width in units
     of theta, the last one open-ended) and Q_i the fraction of the counts.
     P_i is the difference of the exact CDF of eq:CDF at the bin edges, which is
-    the integral of eq:kappax over the bin.  Host-side post-processing of the
-    nbins + 1 counts (scipy's regularized incomplete beta)."""
+    the integral of eq:kappax over the bin; for kappa = inf (Maxwell) it is
+    the regularized incomplete gamma P(3/2, x).  Host-side post-processing of
+    the nbins + 1 counts (scipy's special functions)."""
+    import math
+
     import numpy as np
     from scipy import special
     c = counts.detach().cpu().numpy().astype(np.float64) if hasattr(counts, "detach") else np.asarray(counts, float)
     nb = c.size - 1
     x = (np.arange(nb + 1) * bin_width) ** 2
-    cdf = special.betainc(1.5, kappa - 0.5, x / (x + kappa))
     p = np.empty(nb + 1)
-    p[:nb] = np.diff(cdf)
-    xe = x[-1]
-    p[nb] = special.betainc(kappa - 0.5, 1.5, kappa / (xe + kappa))  # 1 - F at the last edge
+    if math.isinf(kappa):
+        p[:nb] = np.diff(special.gammainc(1.5, x))
+        p[nb] = special.gammaincc(1.5, x[-1])
+    else:
+        cdf = special.betainc(1.5, kappa - 0.5, x / (x + kappa))
+        p[:nb] = np.diff(cdf)
+        p[nb] = special.betainc(kappa - 0.5, 1.5, kappa / (x[-1] + kappa))  # 1 - F at the last edge
     q = c / c.sum()
     return float(np.sum((p + eps) * np.log((p + eps) / (q + eps))))

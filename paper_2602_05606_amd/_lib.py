@@ -36,6 +36,14 @@ class Segment(ctypes.Structure):
     ]
 
 
+class Cell(ctypes.Structure):
+    """kappa_cell: the box [lo, lo + size) a segment's positions are drawn in."""
+    _fields_ = [
+        ("lo", ctypes.c_double * 3),
+        ("size", ctypes.c_double * 3),
+    ]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -54,6 +62,11 @@ SIGNATURES = {
     "kappa_plan_shape": (_st, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "kappa_plan_set_shape": (_st, [_vp, _i, _i, _i]),
     "kappa_plan_destroy": (_st, [_vp]),
+    "kappa_plan_set_cells": (_st, [_vp, ctypes.POINTER(Cell)]),
+    "kappa_plan_launch_pic": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "kappa_plan_graph_launch_pic": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "kappa_load_particles": (_st, [ctypes.POINTER(Segment), ctypes.POINTER(Cell), _u32, _u64, _i,
+                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "kappa_sample_batched": (_st, [ctypes.POINTER(Segment), _u32, _u64, _i, _vp, _vp, _vp, _vp]),
     "kappa_backward_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "kappa_sample_backward": (_st, [_d, _d, _u64, _u64, _u64, _u32, _i, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),

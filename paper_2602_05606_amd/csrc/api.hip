@@ -17,6 +17,9 @@ kappa_status kappa_plan_shape_impl(kappa_plan, int *, int *, int *);
 kappa_status kappa_plan_set_shape_impl(kappa_plan, int, int, int);
 kappa_status kappa_plan_total_impl(kappa_plan, uint64_t *);
 kappa_status kappa_plan_destroy_impl(kappa_plan);
+kappa_status kappa_plan_set_cells_impl(kappa_plan, const kappa_cell *);
+kappa_status kappa_plan_launch_pic_impl(kappa_plan, void *, void *, void *, void *, void *, void *, void *);
+kappa_status kappa_plan_graph_launch_pic_impl(kappa_plan, void *, void *, void *, void *, void *, void *, void *);
 }
 
 namespace kappa {
@@ -31,6 +34,8 @@ int g_dev_state[kMaxDevices] = {0};  // 0 unknown, 1 gfx950, -1 other
 int g_dev_cus[kMaxDevices] = {0};
 
 bool kappa_ok(double kappa) { return std::isfinite(kappa) && kappa > 1.5; }
+// The sampler also takes kappa = +inf, the Maxwell limit.
+bool kappa_or_maxwell_ok(double kappa) { return kappa > 1.5 && !std::isnan(kappa); }
 bool theta_ok(double theta) { return std::isfinite(theta) && theta > 0.0; }
 bool precision_ok(int p) { return p == KAPPA_FP64 || p == KAPPA_FP32 || p == KAPPA_FP32_NOTAIL; }
 size_t elem_size(int p) { return p == KAPPA_FP64 ? 8 : 4; }
@@ -130,7 +135,7 @@ const char *kappa_status_string(kappa_status status)
 
 kappa_status kappa_params(double kappa, double *out)
 {
-    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!kappa_or_maxwell_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be > 3/2 or +inf (got %g)", kappa);
     if (!out) return fail(KAPPA_EINVAL, "null output array");
     const Setup s = make_setup(kappa);
     out[KAPPA_P_KSTAR] = s.kstar;
@@ -148,7 +153,7 @@ kappa_status kappa_params(double kappa, double *out)
 kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
                           uint32_t seg_id, int precision, void *vx, void *vy, void *vz, void *stream)
 {
-    if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
+    if (!kappa_or_maxwell_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be > 3/2 or +inf (got %g)", kappa);
     if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
     if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
     if (n > 0 && counter_offset > UINT64_MAX - (n - 1))
@@ -344,7 +349,7 @@ static kappa_status validate_segments(const kappa_segment *segs, uint32_t nseg, 
     uint64_t total = 0;
     for (uint32_t s = 0; s < nseg; ++s) {
         const kappa_segment &g = segs[s];
-        if (!kappa_ok(g.kappa)) return fail(KAPPA_EINVAL, "segment %u: kappa must be finite and > 3/2", s);
+        if (!kappa_or_maxwell_ok(g.kappa)) return fail(KAPPA_EINVAL, "segment %u: kappa must be > 3/2 or +inf", s);
         if (!theta_ok(g.theta)) return fail(KAPPA_EINVAL, "segment %u: theta must be finite and > 0", s);
         if (!std::isfinite(g.drift[0]) || !std::isfinite(g.drift[1]) || !std::isfinite(g.drift[2]))
             return fail(KAPPA_EINVAL, "segment %u: drift must be finite", s);
@@ -404,6 +409,26 @@ kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int gr
     return kappa_plan_set_shape_impl(plan, block, unroll, grid);
 }
 
+kappa_status kappa_plan_set_cells(kappa_plan plan, const kappa_cell *cells)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_set_cells_impl(plan, cells);
+}
+
+kappa_status kappa_plan_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx, void *vy, void *vz,
+                                   void *stream)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_launch_pic_impl(plan, px, py, pz, vx, vy, vz, stream);
+}
+
+kappa_status kappa_plan_graph_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx, void *vy, void *vz,
+                                         void *stream)
+{
+    if (!plan) return fail(KAPPA_EINVAL, "null plan");
+    return kappa_plan_graph_launch_pic_impl(plan, px, py, pz, vx, vy, vz, stream);
+}
+
 kappa_status kappa_plan_destroy(kappa_plan plan)
 {
     if (!plan) return KAPPA_OK;
@@ -417,6 +442,21 @@ kappa_status kappa_sample_batched(const kappa_segment *segs, uint32_t nseg, uint
     kappa_status st = kappa_plan_create(segs, nseg, seed, precision, &plan);
     if (st != KAPPA_OK) return st;
     st = kappa_plan_launch_impl(plan, vx, vy, vz, stream);
+    if (st == KAPPA_OK) st = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+    kappa_plan_destroy_impl(plan);
+    return st;
+}
+
+kappa_status kappa_load_particles(const kappa_segment *segs, const kappa_cell *cells, uint32_t nseg, uint64_t seed,
+                                  int precision, void *px, void *py, void *pz, void *vx, void *vy, void *vz,
+                                  void *stream)
+{
+    if (!cells) return fail(KAPPA_EINVAL, "null cells");
+    kappa_plan plan = nullptr;
+    kappa_status st = kappa_plan_create(segs, nseg, seed, precision, &plan);
+    if (st != KAPPA_OK) return st;
+    st = kappa_plan_set_cells_impl(plan, cells);
+    if (st == KAPPA_OK) st = kappa_plan_launch_pic_impl(plan, px, py, pz, vx, vy, vz, stream);
     if (st == KAPPA_OK) st = check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
     kappa_plan_destroy_impl(plan);
     return st;

@@ -12,6 +12,13 @@
 //
 // The launch can be captured once into a hipGraph and replayed; the shape
 // (block, particles per thread, grid) is chosen by a timing sweep.
+//
+// Fused particle loading (positions with the velocities, for PIC start-up):
+// when the plan holds a cell box per segment, the same launch also writes
+// px, py, pz = lo + u * size with u from the block of draw 1 of the
+// particle's counter (velocities use draw 0, so they are unchanged).
+// u = (r + 1/2) 2^-32 in FP64; in FP32 u = (floor(r / 2^9) + 1/2) 2^-23,
+// exact in float and below 1.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -40,6 +47,14 @@ struct alignas(16) SegF64 {
     double kstar, inv_kstar, a, b, c, half_inv_b, theta, dx, dy, dz;
 };
 
+struct CellF32 {
+    float lo[3], size[3];
+};
+
+struct CellF64 {
+    double lo[3], size[3];
+};
+
 struct BatchArgs {
     uint64_t total;
     uint32_t k0, k1;
@@ -49,7 +64,10 @@ struct BatchArgs {
     const SegF32 *seg32;     // nseg
     const SegF64 *seg64;     // nseg
     const uint32_t *seg_ids; // nseg
+    const CellF32 *cell32;   // nseg, positions only
+    const CellF64 *cell64;   // nseg, positions only
     void *vx, *vy, *vz;
+    void *px, *py, *pz;      // positions only
 };
 
 // Largest s in [lo, hi] with start[s] <= j (start[lo] <= j holds).
@@ -101,7 +119,42 @@ struct SegParams {
     __device__ __forceinline__ void load(const BatchArgs &a, uint32_t s) { q = a.seg32[s]; }
 };
 
-template <int MODE, int U>
+template <int MODE>
+struct CellParams {
+    CellF32 q;
+    __device__ __forceinline__ void load(const BatchArgs &a, uint32_t s) { q = a.cell32[s]; }
+    // u = (floor(r / 2^9) + 1/2) 2^-23: a 24-bit dyadic, exact in float, in (0, 1)
+    __device__ __forceinline__ float coord(int k, uint32_t r) const
+    {
+        const float u = fmaf(static_cast<float>(r >> 9), 0x1p-23f, 0x1p-24f);
+        return fmaf(u, q.size[k], q.lo[k]);
+    }
+};
+
+template <>
+struct CellParams<kModeF64> {
+    CellF64 q;
+    __device__ __forceinline__ void load(const BatchArgs &a, uint32_t s) { q = a.cell64[s]; }
+    __device__ __forceinline__ double coord(int k, uint32_t r) const
+    {
+        const double u = fma(static_cast<double>(r), 0x1p-32, 0x1p-33);
+        return fma(u, q.size[k], q.lo[k]);
+    }
+};
+
+template <typename T, int U>
+__device__ __forceinline__ void store_or_tail(T *p, uint64_t j0, uint64_t total, const T (&v)[U])
+{
+    if (j0 + U <= total) {
+        store_group_b<T, U>(p + j0, v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k < total) p[j0 + k] = v[k];
+    }
+}
+
+template <int MODE, int U, bool POS>
 __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
 {
     using T = typename std::conditional<MODE == kModeF64, double, float>::type;
@@ -118,7 +171,10 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
         uint32_t seg_id = a.seg_ids[s];
         SegParams<MODE> prm;
         prm.load(a, s);
+        CellParams<MODE> cell;
+        if constexpr (POS) cell.load(a, s);
         T x[U], y[U], z[U];
+        T qx[U], qy[U], qz[U];  // positions (POS only)
         uint32_t seg_of[U];
         uint32_t tails = 0;
 #pragma unroll
@@ -126,6 +182,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
             const uint64_t j = j0 + k;
             if (j >= a.total) {
                 x[k] = y[k] = z[k] = T(0);
+                if constexpr (POS) qx[k] = qy[k] = qz[k] = T(0);
                 seg_of[k] = s;
                 continue;
             }
@@ -138,8 +195,15 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 seg_begin = a.start[s];
                 seg_id = a.seg_ids[s];
                 prm.load(a, s);
+                if constexpr (POS) cell.load(a, s);
             }
             seg_of[k] = s;
+            if constexpr (POS) {
+                const Block4 bp = particle_block(j - seg_begin, seg_id, 1, a.k0, a.k1);
+                qx[k] = cell.coord(0, bp.r0);
+                qy[k] = cell.coord(1, bp.r1);
+                qz[k] = cell.coord(2, bp.r2);
+            }
             const Block4 b = particle_block(j - seg_begin, seg_id, 0, a.k0, a.k1);
             const auto &q = prm.q;
             if constexpr (MODE == kModeF64) {
@@ -180,43 +244,43 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 }
             }
         }
-        if (j0 + U <= a.total) {
-            store_group_b<T, U>(vx + j0, x);
-            store_group_b<T, U>(vy + j0, y);
-            store_group_b<T, U>(vz + j0, z);
-        } else {
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                if (j0 + k < a.total) {
-                    vx[j0 + k] = x[k];
-                    vy[j0 + k] = y[k];
-                    vz[j0 + k] = z[k];
-                }
-            }
+        store_or_tail<T, U>(vx, j0, a.total, x);
+        store_or_tail<T, U>(vy, j0, a.total, y);
+        store_or_tail<T, U>(vz, j0, a.total, z);
+        if constexpr (POS) {
+            store_or_tail<T, U>(static_cast<T *>(a.px), j0, a.total, qx);
+            store_or_tail<T, U>(static_cast<T *>(a.py), j0, a.total, qy);
+            store_or_tail<T, U>(static_cast<T *>(a.pz), j0, a.total, qz);
         }
     }
 }
 
-template <int MODE>
+template <int MODE, bool POS>
 hipError_t launch_batched_mode(const Shape &sh, const BatchArgs &a, hipStream_t stream)
 {
     dim3 grid(sh.grid), block(sh.block);
     switch (sh.unroll) {
-    case 1: hipLaunchKernelGGL((batched_kernel<MODE, 1>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((batched_kernel<MODE, 2>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((batched_kernel<MODE, 4>), grid, block, 0, stream, a); break;
-    case 8: hipLaunchKernelGGL((batched_kernel<MODE, 8>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((batched_kernel<MODE, 1, POS>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((batched_kernel<MODE, 2, POS>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((batched_kernel<MODE, 4, POS>), grid, block, 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((batched_kernel<MODE, 8, POS>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int MODE>
+hipError_t launch_batched_pos(const Shape &sh, const BatchArgs &a, hipStream_t stream)
+{
+    return a.px ? launch_batched_mode<MODE, true>(sh, a, stream) : launch_batched_mode<MODE, false>(sh, a, stream);
+}
+
 hipError_t launch_batched(int mode, const Shape &sh, const BatchArgs &a, hipStream_t stream)
 {
     switch (mode) {
-    case kModeF64: return launch_batched_mode<kModeF64>(sh, a, stream);
-    case kModeF32: return launch_batched_mode<kModeF32>(sh, a, stream);
-    case kModeF32NoTail: return launch_batched_mode<kModeF32NoTail>(sh, a, stream);
+    case kModeF64: return launch_batched_pos<kModeF64>(sh, a, stream);
+    case kModeF32: return launch_batched_pos<kModeF32>(sh, a, stream);
+    case kModeF32NoTail: return launch_batched_pos<kModeF32NoTail>(sh, a, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -297,11 +361,15 @@ struct kappa_plan_s {
     const kappa::SegF32 *seg32 = nullptr;
     const kappa::SegF64 *seg64 = nullptr;
     const uint32_t *seg_ids = nullptr;
-    // captured graph
+    // cell boxes for fused particle loading (kappa_plan_set_cells)
+    void *cell_block = nullptr;
+    const kappa::CellF32 *cell32 = nullptr;
+    const kappa::CellF64 *cell64 = nullptr;
+    // captured graph and the outputs it was captured for
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;
-    void *g_vx = nullptr, *g_vy = nullptr, *g_vz = nullptr;
+    void *g_out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     kappa::Shape g_shape{0, 0, 0};
 };
 
@@ -309,7 +377,13 @@ namespace kappa {
 
 namespace {
 
-BatchArgs batch_args(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+// Outputs of one launch: velocities, and positions when pos[0] is non-null.
+struct Outputs {
+    void *v[3];
+    void *pos[3];
+};
+
+BatchArgs batch_args(const kappa_plan_s *p, const Outputs &o)
 {
     BatchArgs a;
     a.total = p->total;
@@ -321,9 +395,14 @@ BatchArgs batch_args(const kappa_plan_s *p, void *vx, void *vy, void *vz)
     a.seg32 = p->seg32;
     a.seg64 = p->seg64;
     a.seg_ids = p->seg_ids;
-    a.vx = vx;
-    a.vy = vy;
-    a.vz = vz;
+    a.cell32 = p->cell32;
+    a.cell64 = p->cell64;
+    a.vx = o.v[0];
+    a.vy = o.v[1];
+    a.vz = o.v[2];
+    a.px = o.pos[0];
+    a.py = o.pos[1];
+    a.pz = o.pos[2];
     return a;
 }
 
@@ -341,21 +420,24 @@ Shape default_batched_shape(int mode, uint64_t total)
     return s;
 }
 
-bool aligned_for(int mode, const Shape &s, void *vx, void *vy, void *vz)
+bool aligned_for(int mode, const Shape &s, const Outputs &o)
 {
     const size_t esz = mode == kModeF64 ? 8 : 4;
     const size_t bytes = esz * s.unroll;
     const size_t need = bytes >= 16 ? 16 : bytes;
-    return reinterpret_cast<uintptr_t>(vx) % need == 0 && reinterpret_cast<uintptr_t>(vy) % need == 0 &&
-           reinterpret_cast<uintptr_t>(vz) % need == 0;
+    for (int k = 0; k < 3; ++k) {
+        if (reinterpret_cast<uintptr_t>(o.v[k]) % need) return false;
+        if (o.pos[0] && reinterpret_cast<uintptr_t>(o.pos[k]) % need) return false;
+    }
+    return true;
 }
 
 // Shape actually launched: falls back to one particle per thread when the
 // outputs are not aligned for the group's vector store.
-Shape effective_shape(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+Shape effective_shape(const kappa_plan_s *p, const Outputs &o)
 {
     Shape s = p->shape;
-    if (!aligned_for(p->mode, s, vx, vy, vz)) s.unroll = 1;
+    if (!aligned_for(p->mode, s, o)) s.unroll = 1;
     return s;
 }
 
@@ -467,36 +549,42 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
 
 namespace kappa {
 namespace {
-kappa_status check_plan_outputs(const kappa_plan_s *p, void *vx, void *vy, void *vz)
+kappa_status check_plan_outputs(const kappa_plan_s *p, const Outputs &o)
 {
     if (p->total == 0) return KAPPA_OK;
-    if (!vx || !vy || !vz) return fail(KAPPA_EINVAL, "null output pointer for a plan of %llu particles",
-                                       (unsigned long long)p->total);
+    const bool pos = o.pos[0] || o.pos[1] || o.pos[2];
+    for (int k = 0; k < 3; ++k) {
+        if (!o.v[k]) return fail(KAPPA_EINVAL, "null velocity pointer for a plan of %llu particles",
+                                 (unsigned long long)p->total);
+        if (pos && !o.pos[k]) return fail(KAPPA_EINVAL, "null position pointer");
+    }
+    if (pos && !p->cell_block) return fail(KAPPA_EINVAL, "positions asked for but the plan has no cells "
+                                                         "(kappa_plan_set_cells)");
     const size_t e = p->mode == kModeF64 ? 8 : 4;
-    if (reinterpret_cast<uintptr_t>(vx) % e || reinterpret_cast<uintptr_t>(vy) % e ||
-        reinterpret_cast<uintptr_t>(vz) % e)
-        return fail(KAPPA_EALIGN, "output pointers must be aligned to %zu bytes", e);
+    for (int k = 0; k < 3; ++k)
+        if (reinterpret_cast<uintptr_t>(o.v[k]) % e || (pos && reinterpret_cast<uintptr_t>(o.pos[k]) % e))
+            return fail(KAPPA_EALIGN, "output pointers must be aligned to %zu bytes", e);
     return KAPPA_OK;
 }
-}  // namespace
-}  // namespace kappa
 
-extern "C" kappa_status kappa_plan_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+kappa_status plan_launch(kappa_plan p, const Outputs &o, void *stream)
 {
-    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    const kappa_status cs = check_plan_outputs(p, o);
     if (cs != KAPPA_OK || p->total == 0) return cs;
-    const Shape s = effective_shape(p, vx, vy, vz);
-    return check_hip(launch_batched(p->mode, s, batch_args(p, vx, vy, vz), static_cast<hipStream_t>(stream)),
+    const Shape s = effective_shape(p, o);
+    return check_hip(launch_batched(p->mode, s, batch_args(p, o), static_cast<hipStream_t>(stream)),
                      "batched kernel launch");
 }
 
-extern "C" kappa_status kappa_plan_graph_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+// Captures the launch for these outputs and shape once, then replays it.
+kappa_status plan_graph_launch(kappa_plan p, const Outputs &o, void *stream)
 {
-    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    const kappa_status cs = check_plan_outputs(p, o);
     if (cs != KAPPA_OK || p->total == 0) return cs;
-    const Shape s = effective_shape(p, vx, vy, vz);
-    const bool stale = !p->exec || p->g_vx != vx || p->g_vy != vy || p->g_vz != vz || p->g_shape.block != s.block ||
-                       p->g_shape.unroll != s.unroll || p->g_shape.grid != s.grid;
+    const Shape s = effective_shape(p, o);
+    const void *want[6] = {o.v[0], o.v[1], o.v[2], o.pos[0], o.pos[1], o.pos[2]};
+    bool stale = !p->exec || p->g_shape.block != s.block || p->g_shape.unroll != s.unroll || p->g_shape.grid != s.grid;
+    for (int k = 0; k < 6; ++k) stale = stale || p->g_out[k] != want[k];
     if (stale) {
         drop_graph(p);
         kappa_status st;
@@ -506,7 +594,7 @@ extern "C" kappa_status kappa_plan_graph_launch_impl(kappa_plan p, void *vx, voi
         }
         st = check_hip(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         if (st != KAPPA_OK) return st;
-        const hipError_t le = launch_batched(p->mode, s, batch_args(p, vx, vy, vz), p->capture_stream);
+        const hipError_t le = launch_batched(p->mode, s, batch_args(p, o), p->capture_stream);
         const hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
         if (le != hipSuccess) return check_hip(le, "batched kernel capture");
         st = check_hip(ce, "hipStreamEndCapture");
@@ -516,17 +604,91 @@ extern "C" kappa_status kappa_plan_graph_launch_impl(kappa_plan p, void *vx, voi
             drop_graph(p);
             return st;
         }
-        p->g_vx = vx;
-        p->g_vy = vy;
-        p->g_vz = vz;
+        for (int k = 0; k < 6; ++k) p->g_out[k] = const_cast<void *>(want[k]);
         p->g_shape = s;
     }
     return check_hip(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
 }
 
+Outputs velocities(void *vx, void *vy, void *vz) { return Outputs{{vx, vy, vz}, {nullptr, nullptr, nullptr}}; }
+}  // namespace
+}  // namespace kappa
+
+extern "C" kappa_status kappa_plan_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+{
+    return plan_launch(p, velocities(vx, vy, vz), stream);
+}
+
+extern "C" kappa_status kappa_plan_graph_launch_impl(kappa_plan p, void *vx, void *vy, void *vz, void *stream)
+{
+    return plan_graph_launch(p, velocities(vx, vy, vz), stream);
+}
+
+extern "C" kappa_status kappa_plan_launch_pic_impl(kappa_plan p, void *px, void *py, void *pz, void *vx, void *vy,
+                                                   void *vz, void *stream)
+{
+    return plan_launch(p, Outputs{{vx, vy, vz}, {px, py, pz}}, stream);
+}
+
+extern "C" kappa_status kappa_plan_graph_launch_pic_impl(kappa_plan p, void *px, void *py, void *pz, void *vx,
+                                                         void *vy, void *vz, void *stream)
+{
+    return plan_graph_launch(p, Outputs{{vx, vy, vz}, {px, py, pz}}, stream);
+}
+
+extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell *cells)
+{
+    if (p->cell_block) {
+        // a captured graph may still read the old table
+        drop_graph(p);
+        kappa_status st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (st != KAPPA_OK) return st;
+        hipFree(p->cell_block);
+        p->cell_block = nullptr;
+        p->cell32 = nullptr;
+        p->cell64 = nullptr;
+    }
+    if (!cells) return KAPPA_OK;
+    for (uint32_t s = 0; s < p->nseg; ++s)
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(cells[s].lo[k]) || !std::isfinite(cells[s].size[k]) || cells[s].size[k] < 0.0)
+                return fail(KAPPA_EINVAL, "cell %u: lo must be finite and size finite and >= 0", s);
+    std::vector<CellF32> c32(p->nseg);
+    std::vector<CellF64> c64(p->nseg);
+    for (uint32_t s = 0; s < p->nseg; ++s)
+        for (int k = 0; k < 3; ++k) {
+            c64[s].lo[k] = cells[s].lo[k];
+            c64[s].size[k] = cells[s].size[k];
+            c32[s].lo[k] = static_cast<float>(cells[s].lo[k]);
+            c32[s].size[k] = static_cast<float>(cells[s].size[k]);
+        }
+    const size_t o64 = (c32.size() * sizeof(CellF32) + 255) & ~static_cast<size_t>(255);
+    const size_t bytes = o64 + c64.size() * sizeof(CellF64);
+    if (hipMalloc(&p->cell_block, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->cell_block = nullptr;
+        return fail(KAPPA_ENOMEM, "hipMalloc of %zu bytes for the cell table failed", bytes);
+    }
+    std::vector<unsigned char> host(bytes, 0);
+    std::memcpy(host.data(), c32.data(), c32.size() * sizeof(CellF32));
+    std::memcpy(host.data() + o64, c64.data(), c64.size() * sizeof(CellF64));
+    kappa_status st = check_hip(hipMemcpy(p->cell_block, host.data(), bytes, hipMemcpyHostToDevice),
+                                "hipMemcpy cell table");
+    if (st != KAPPA_OK) {
+        hipFree(p->cell_block);
+        p->cell_block = nullptr;
+        return st;
+    }
+    auto *base = static_cast<unsigned char *>(p->cell_block);
+    p->cell32 = reinterpret_cast<const CellF32 *>(base);
+    p->cell64 = reinterpret_cast<const CellF64 *>(base + o64);
+    return KAPPA_OK;
+}
+
 extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *vy, void *vz, int reps, void *stream)
 {
-    const kappa_status cs = check_plan_outputs(p, vx, vy, vz);
+    const Outputs o = velocities(vx, vy, vz);
+    const kappa_status cs = check_plan_outputs(p, o);
     if (cs != KAPPA_OK || p->total == 0) return cs;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
@@ -550,8 +712,8 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
                 const uint64_t need = (groups + b - 1) / b;
                 Shape cand{b, u, w > 0 ? w * cus : static_cast<int>(std::min<uint64_t>(need, 1ull << 30))};
                 if (w > 0 && static_cast<uint64_t>(cand.grid) >= need) continue;  // same as one pass
-                if (!aligned_for(p->mode, cand, vx, vy, vz)) continue;
-                const BatchArgs a = batch_args(p, vx, vy, vz);
+                if (!aligned_for(p->mode, cand, o)) continue;
+                const BatchArgs a = batch_args(p, o);
                 hipError_t err = launch_batched(p->mode, cand, a, st);  // warm-up
                 if (err != hipSuccess) {
                     s = check_hip(err, "autotune launch");
@@ -611,6 +773,7 @@ extern "C" kappa_status kappa_plan_destroy_impl(kappa_plan p)
     drop_graph(p);
     if (p->capture_stream) hipStreamDestroy(p->capture_stream);
     if (p->dev_block) hipFree(p->dev_block);
+    if (p->cell_block) hipFree(p->cell_block);
     delete p;
     return KAPPA_OK;
 }

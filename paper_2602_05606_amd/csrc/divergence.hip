@@ -6,7 +6,8 @@
 //
 // For a free c the other parameters stay as Table 1 sets them: a of eq:a,
 // kappa* of eq:k2, b = (b/c) c with b/c of eq:b.  f is eq:kappax and g is
-// eq:approx_x, both in x = v^2/theta^2.
+// eq:approx_x, both in x = v^2/theta^2.  kappa = +inf is the Maxwell limit:
+// f = 2/sqrt(pi) x^(1/2) e^-x, exp_q* -> exp, a and b/c at their limits.
 //
 // Quadrature.  x = exp(ell), ell = (pi/2) sinh(t) (the exp-sinh rule for
 // [0, inf)), trapezoidal in t with step 1/16 over t in [-83/16, 108/16]: 192
@@ -52,24 +53,33 @@ struct DivNode {
 
 struct KappaConst {
     double kappa, kstar, lnB, a, b_over_c;
-    bool ok;
+    bool ok, maxwell;
 };
 
 __device__ KappaConst kappa_const(double k)
 {
     KappaConst s;
-    s.ok = isfinite(k) && k > 1.5;
+    s.ok = k > 1.5 && !isnan(k);
+    s.maxwell = isinf(k);
     s.kappa = k;
     s.kstar = k - 0.5;                                                 // eq:k2
     if (!s.ok) return s;
+    if (s.maxwell) {
+        s.lnB = 0.0;
+        s.a = 0.82713398786586665;  // (4 / (3 sqrt(pi)))^(2/3)
+        s.b_over_c = 1.0;
+        return s;
+    }
     s.lnB = lgamma(1.5) + lgamma(s.kstar) - lgamma(k + 1.0);           // B(3/2, kappa - 1/2)
     s.a = exp(-log(k) + (2.0 / 3.0) * (log(2.0 / 3.0) - s.lnB));       // eq:a
     s.b_over_c = exp((log(1.5 * s.kstar) + s.lnB) / s.kstar) * s.kstar / k;  // eq:b
     return s;
 }
 
+// The c the sampler uses: eq:c, or the Maxwell-limit constant for kappa = inf.
 __device__ double c_from_eq_c(double k)
 {
+    if (isinf(k)) return kMaxwellC;
     return (0.123 * k * k - 1.12 * k + 2.56) / (k * k - 7.89 * k + 15.6);  // eq:c
 }
 
@@ -109,8 +119,9 @@ __global__ void __launch_bounds__(256) divergence_kernel(const double *__restric
             const double t = (n - kDivNeg) * kDivH;
             const double ell = kHalfPi * sinh(t);
             const double x = exp(ell);
-            // eq:kappax in logs
-            const double lnf = -lnk - s.lnB + 0.5 * (ell - lnk) - (s.kappa + 1.0) * log1p(x / s.kappa);
+            // eq:kappax in logs; Maxwell: ln(2/sqrt(pi)) + ell/2 - x
+            const double lnf = s.maxwell ? 0.12078223763524522 + 0.5 * ell - x
+                                         : -lnk - s.lnB + 0.5 * (ell - lnk) - (s.kappa + 1.0) * log1p(x / s.kappa);
             const double wf = kDivH * kHalfPi * cosh(t) * x * exp(lnf);  // h dx/dt f(x)
             nodes[n] = DivNode{x, exp(-ell), lnf, wf, wf * x};
         }
@@ -120,6 +131,7 @@ __global__ void __launch_bounds__(256) divergence_kernel(const double *__restric
     const uint32_t j0 = blockIdx.x * kDivCPerBlock;
     const uint32_t j1 = j0 + kDivCPerBlock < nc ? j0 + kDivCPerBlock : nc;
     const double kstar = s.kstar, inv_kstar = 1.0 / s.kstar;
+    const bool maxwell = s.maxwell;
     for (uint32_t j = j0 + wave; j < j1; j += nwaves) {
         const double c = cvals ? cvals[j] : (s.ok ? c_from_eq_c(s.kappa) : 0.0);
         double dsum = 0.0, esum = 0.0;
@@ -128,13 +140,25 @@ __global__ void __launch_bounds__(256) divergence_kernel(const double *__restric
             const double a = s.a, b = s.b_over_c * c;
             for (int n = lane; n < kDivNodes; n += 64) {
                 const DivNode nd = nodes[n];
+                // f has underflowed (Maxwell: x > 745): the node adds nothing, and delta
+                // = ln g - ln f would be the difference of two numbers of order x
+                if (nd.w_d == 0.0) continue;
                 const double inv = 1.0 / (1.0 + c * nd.x);
                 const double t1 = nd.x * inv;                      // x / (1 + c x) <= 1/c
                 const double y = (a + b * nd.x) * t1;
-                const double sl = log1p(y * inv_kstar);
-                const double ln1mE = log(-expm1(-kstar * sl));
+                // ln exp_q*(-y) = -kappa* log1p(y / kappa*), and ln of the (kappa*+1) power; -y for Maxwell
+                double lq, lq1;
+                if (maxwell) {
+                    lq = -y;
+                    lq1 = -y;
+                } else {
+                    const double sl = log1p(y * inv_kstar);
+                    lq = -kstar * sl;
+                    lq1 = -(kstar + 1.0) * sl;
+                }
+                const double ln1mE = log(-expm1(lq));
                 const double yp = (a * nd.q + 2.0 * b + b * c * nd.x) * t1 * inv;
-                const double lng = 0.40546510810816438 + 0.5 * ln1mE - (kstar + 1.0) * sl + log(yp);  // ln(3/2) + ...
+                const double lng = 0.40546510810816438 + 0.5 * ln1mE + lq1 + log(yp);  // ln(3/2) + ...
                 double em1_minus_d, em1;
                 expm1_parts(lng - nd.lnf, em1_minus_d, em1);
                 dsum += nd.w_d * em1_minus_d;
@@ -147,7 +171,8 @@ __global__ void __launch_bounds__(256) divergence_kernel(const double *__restric
             const size_t o = static_cast<size_t>(i) * nc + j;
             const double nan = __builtin_nan("");
             D[o] = ok ? dsum : nan;
-            if (dE) dE[o] = ok ? esum * (2.0 * s.kappa - 3.0) / (3.0 * s.kappa) : nan;
+            const double inv_energy = s.maxwell ? 2.0 / 3.0 : (2.0 * s.kappa - 3.0) / (3.0 * s.kappa);
+            if (dE) dE[o] = ok ? esum * inv_energy : nan;
         }
     }
 }

@@ -25,6 +25,17 @@ Setup make_setup(double kappa)
 {
     Setup s{};
     s.kappa = kappa;
+    if (std::isinf(kappa)) {
+        // Maxwell limit: exp_q* -> exp, ln_q* -> ln; a and b/c at their kappa -> inf
+        // limits (Sec. 3); c minimises the relative entropy against the Maxwell density.
+        s.kstar = kappa;
+        s.lnbeta = -kappa;
+        s.a = std::pow(4.0 / (3.0 * std::sqrt(M_PI)), 2.0 / 3.0);
+        s.c = kMaxwellC;
+        s.b_over_c = 1.0;
+        s.b = s.c;
+        return s;  // derivatives stay 0: kappa = inf is not differentiated
+    }
     // kappa* = kappa - 1/2 (eq:k2)
     s.kstar = kappa - 0.5;
     // ln B(3/2, kappa*) with B(x, y) = Gamma(x) Gamma(y) / Gamma(x + y) (Sec. 6)
@@ -53,11 +64,16 @@ Setup make_setup(double kappa)
     return s;
 }
 
+// The kernels evaluate L = -kappa* expm1(-lT / kappa*).  For kappa = inf they
+// get kappa* = 2^60: then L = lT (1 + O(|lT| 2^-61)), lT within (-38, 0), which
+// is lT to below half an ulp in FP64 and FP32, with no special case on the GPU.
+static double kernel_kstar(const Setup &s) { return std::isinf(s.kstar) ? 0x1p60 : s.kstar; }
+
 SpeciesF64 species_f64(const Setup &s, double theta)
 {
     SpeciesF64 p{};
-    p.kstar = s.kstar;
-    p.inv_kstar = 1.0 / s.kstar;
+    p.kstar = kernel_kstar(s);
+    p.inv_kstar = 1.0 / p.kstar;
     p.a = s.a;
     p.b = s.b;
     p.c = s.c;
@@ -72,14 +88,15 @@ SpeciesF64 species_f64(const Setup &s, double theta)
 SpeciesF32 species_f32(const Setup &s, double theta)
 {
     SpeciesF32 p{};
-    p.kstar = static_cast<float>(s.kstar);
-    p.inv_kstar = static_cast<float>(1.0 / s.kstar);
+    const double ks = kernel_kstar(s);
+    p.kstar = static_cast<float>(ks);
+    p.inv_kstar = static_cast<float>(1.0 / ks);
     p.a = static_cast<float>(s.a);
     p.b = static_cast<float>(s.b);
     p.c = static_cast<float>(s.c);
     p.half_inv_b = static_cast<float>(0.5 / s.b);
     p.theta = static_cast<float>(theta);
-    p.ln2_inv_kstar = static_cast<float>(0.6931471805599453 / s.kstar);
+    p.ln2_inv_kstar = static_cast<float>(0.6931471805599453 / ks);
     p.two_b = static_cast<float>(2.0 * s.b);
     p.four_b = static_cast<float>(4.0 * s.b);
     p.da = static_cast<float>(s.da);

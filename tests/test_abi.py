@@ -67,13 +67,26 @@ FAKE_ODD = ctypes.c_void_p(0x10001)
 
 @pytest.mark.parametrize("kappa,theta,prec,code", [
     (1.5, 1.0, 1, _lib.EINVAL), (1.0, 1.0, 1, _lib.EINVAL), (math.nan, 1.0, 1, _lib.EINVAL),
-    (math.inf, 1.0, 1, _lib.EINVAL), (3.0, 0.0, 1, _lib.EINVAL), (3.0, -1.0, 1, _lib.EINVAL),
+    (-math.inf, 1.0, 1, _lib.EINVAL), (3.0, 0.0, 1, _lib.EINVAL), (3.0, -1.0, 1, _lib.EINVAL),
     (3.0, math.nan, 1, _lib.EINVAL), (3.0, 1.0, 7, _lib.EINVAL), (3.0, 1.0, -1, _lib.EINVAL),
 ])
 def test_sample_rejects_bad_arguments(kappa, theta, prec, code):
     lib = _lib.load()
     assert lib.kappa_sample(kappa, theta, 10, 0, 0, 0, prec, FAKE, FAKE, FAKE, None) == code
     assert lib.kappa_last_error()
+
+
+def test_maxwell_limit_is_accepted_where_documented(orc):
+    lib = _lib.load()
+    got, ref = kp.params(math.inf), orc.params(math.inf)
+    assert got == ref
+    # the sampler takes +inf (fails later only for want of a GPU); backward and exact generators do not
+    assert lib.kappa_sample(math.inf, 1.0, 10, 0, 0, 0, 1, FAKE_ODD, FAKE, FAKE, None) == _lib.EALIGN
+    g = ctypes.c_void_p(0x10000)
+    assert lib.kappa_sample_backward(math.inf, 1.0, 10, 0, 0, 0, 1, FAKE, FAKE, FAKE, g, FAKE, 1 << 20,
+                                     None) == _lib.EINVAL
+    assert lib.kappa_sample_exact_t(math.inf, 1.0, 10, 0, 1, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_exact_pareto(math.inf, 1.0, 10, 0, 1, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL
 
 
 def test_sample_pointer_checks():
@@ -166,3 +179,14 @@ def test_workload_tables_shapes():
     assert [s["seg_id"] for s in segs] == list(range(len(segs)))
     chunks = workloads.c5_chunks()
     assert sum(c for _, c in chunks) == 10 ** 9 and len(chunks) == 4
+
+
+def test_pic_argument_checks():
+    lib = _lib.load()
+    assert ctypes.sizeof(_lib.Cell) == 48
+    assert lib.kappa_plan_set_cells(None, None) == _lib.EINVAL
+    assert lib.kappa_plan_launch_pic(None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_plan_graph_launch_pic(None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    segs = (_lib.Segment * 1)()
+    segs[0].kappa, segs[0].theta, segs[0].count = 3.0, 1.0, 10
+    assert lib.kappa_load_particles(segs, None, 1, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL

@@ -48,6 +48,23 @@ def batched_segments(cells=C4["cells"], species=C4["species"], table_seed=C4["ta
     return segs
 
 
+def batched_cells(cells=C4["cells"], species=C4["species"], grid=(16, 16, 16), spacing=(0.5, 0.5, 0.5),
+                  origin=(-4.0, -4.0, -4.0)):
+    """Cell boxes for the C4 segments, in segment order: cell c sits at
+    (c % nx, (c // nx) % ny, c // (nx ny)) of a regular grid of spacing dx
+    (16^3 = 4096 cells of 0.5^3 from -4); every species of a cell shares
+    its box.  Array of shape (cells * species, 2, 3): (lo, size)."""
+    nx, ny, _ = grid
+    out = np.empty((cells * species, 2, 3))
+    for c in range(cells):
+        idx = np.array([c % nx, (c // nx) % ny, c // (nx * ny)], dtype=np.float64)
+        lo = np.asarray(origin) + idx * np.asarray(spacing)
+        for s in range(species):
+            out[species * c + s, 0] = lo
+            out[species * c + s, 1] = spacing
+    return out
+
+
 def upstream_gradient(n, seed=C3["grad_seed"]):
     """dLoss/dv ~ N(0, 1) per component: float32 array of shape (3, n)."""
     return np.random.default_rng(seed).standard_normal((3, n), dtype=np.float32)
