@@ -11,6 +11,11 @@
 
 namespace kappa {
 
+// c of the Maxwell limit kappa = +inf: the minimiser 0.078998 of the relative
+// entropy (eq:relative_entropy) against the Maxwell density, to three figures.
+// make_setup also takes kappa = +inf and returns that limit.
+constexpr double kMaxwellC = 0.079;
+
 enum Mode { kModeF64 = KAPPA_FP64, kModeF32 = KAPPA_FP32, kModeF32NoTail = KAPPA_FP32_NOTAIL };
 
 // Launch shape: threads per block, particles per thread, blocks in the grid

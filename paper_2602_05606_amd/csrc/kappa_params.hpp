@@ -12,12 +12,7 @@ struct Setup {
     double kappa, kstar, a, b, c, b_over_c, da, db, dc, lnbeta;
 };
 
-// c of the Maxwell limit kappa = +inf: the minimiser 0.078998 of the relative
-// entropy (eq:relative_entropy) against the Maxwell density, to three figures.
-constexpr double kMaxwellC = 0.079;
-
-// Host: computes the setup block.  Requires kappa > 3/2 (finite, or +inf for
-// the Maxwell limit).
+// Host: computes the setup block.  Requires kappa > 3/2 and finite.
 Setup make_setup(double kappa);
 
 // Digamma on the host (recurrence + asymptotic series); used for the

@@ -3,6 +3,7 @@
 // the paper computes once per species, in FP64.
 #include <cmath>
 
+#include "kappa_internal.hpp"
 #include "kappa_params.hpp"
 
 namespace kappa {
