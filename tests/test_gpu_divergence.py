@@ -74,7 +74,8 @@ def test_invalid_entries_and_argmin():
     D, dE, am = D.cpu().numpy(), dE.cpu().numpy(), am.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     for i, k in enumerate(ks):
         for j, c in enumerate(cs):
-            bad = not (np.isfinite(k) and k > 1.5 and np.isfinite(c) and c >= 0)
+            # kappa = +inf is the Maxwell limit, a valid row
+            bad = not (k > 1.5 and not np.isnan(k) and np.isfinite(c) and c >= 0)
             assert np.isnan(D[i, j]) == bad and np.isnan(dE[i, j]) == bad, (k, c)
     for i in range(len(ks)):
         row = D[i]
