@@ -116,6 +116,17 @@ def test_ragged_and_misaligned_outputs():
             torch.cuda.synchronize()
             for a, b in zip(pos + vel, views):
                 assert torch.equal(a, b)
+        # a cell of zero size pins its particles to lo (segment 3: 130 particles from offset 8)
+        flat = cells.copy()
+        flat[3, 1] = 0.0
+        with kp.Plan(segs, 5, prec) as plan:
+            plan.set_cells(flat)
+            pos, vel = plan.outputs(), plan.outputs()
+            plan.launch_pic(pos, vel)
+            torch.cuda.synchronize()
+            for k in range(3):
+                assert torch.all(pos[k][8:138] == float(np.asarray(flat[3, 0, k], dtype=np.float32 if prec != kp.FP64
+                                                                     else np.float64)))
 
 
 def test_refused_without_cells(c4):
