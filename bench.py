@@ -284,8 +284,9 @@ EXTRAS = ("rates", "simt", "ks", "test2", "survey", "c5", "fp64", "backward", "b
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed steps first: the GPU clock ramps up over about 20 steps (40 ms) after idle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="same as --extras none")
     ap.add_argument("--extras", default="all",
@@ -303,7 +304,7 @@ def main():
         ap.error(f"unknown extras {sorted(unknown)}; choose from {','.join(EXTRAS)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the generator needs no communication, and a run on N GPUs is "
-              "N independent counter ranges (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "N independent counter ranges. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

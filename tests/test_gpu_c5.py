@@ -7,8 +7,8 @@ At kappa = 1.6 the speed tail falls as v^-2kappa (Sec. 5), so E[v^n] is
 infinite for n >= 2 kappa - 1 = 2.2: the variance of |v|^2 and the fourth
 moments have no population value.  Moments are therefore compared paired (the
 same particles, the same uniforms: every precision draws the same uniforms),
-which isolates the precision error.  Results are printed and written to
-gpurun_out/c5_report.json when that folder exists.
+which isolates the precision error.  Results are printed, and written to
+c5_report.json in the directory named by KAPPA_REPORT_DIR when that is set.
 """
 import json
 import os
@@ -88,8 +88,8 @@ def test_c5_precision_and_tail(orc):
               "ks_speed_fp32_vs_oracle_fp64": ks32, "ks_speed_fp64_vs_oracle_fp64": ks64,
               "fp32_max_norm_relative_error": float(d.max()), "fp32_mean_norm_relative_error": float(d.mean())}
     print(json.dumps(report, indent=1, default=float))
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/c5_report.json", "w") as f:
+    if os.environ.get("KAPPA_REPORT_DIR"):
+        with open(os.path.join(os.environ["KAPPA_REPORT_DIR"], "c5_report.json"), "w") as f:
             json.dump(report, f, indent=1, default=float)
     worst = lambda e: max(v for d_ in e.values() for v in d_.values())
     assert worst(e64) < 1e-12
