@@ -225,6 +225,17 @@ def simt_loop_counts(kp, torch, kappas, theta, seed, n=1 << 24):
     return res
 
 
+def dc_inside(ks):
+    """kappa values where eq:c lies inside the survey's c range [0, 1.5]."""
+    cap = (0.123 * ks ** 2 - 1.12 * ks + 2.56) / (ks ** 2 - 7.89 * ks + 15.6)
+    return cap <= 1.5
+
+
+def dc_all(kp, kt):
+    d, _, _ = kp.divergence_grid(kt, None, energy=False)
+    return d.cpu().numpy()[:, 0]
+
+
 def divergence_survey(kp, torch, dev):
     """The grid search behind eq:c (Sec. 3, Fig. fig:map): D(f||g; kappa, c) on
     c in [0, 1.5] x kappa in (1.5, 10] at steps 0.005 and 0.01, with the
@@ -241,6 +252,10 @@ def divergence_survey(kp, torch, dev):
         kp._ptr(kt), len(ks), kp._ptr(ct), len(cs), kp._ptr(D), None, kp._ptr(am),
         kp._stream(None, dev)), "kappa_divergence_grid"), 3, torch)
     copt = cs[am.cpu().numpy()]
+    # golden-section refinement of the grid optimum (kappa_optimum_c), 40 steps per kappa
+    c_ref, d_ref = kp.optimum_c(kt, ct, iters=40)
+    opt_ms = time_launches(lambda: kp.optimum_c(kt, ct, iters=40), 3, torch)
+    c_ref, d_ref = c_ref.cpu().numpy(), d_ref.cpu().numpy()
     dc, ec, _ = kp.divergence_grid(kt, None)
     dc, ec = dc.cpu().numpy()[:, 0], ec.cpu().numpy()[:, 0]
     pick = [1.6, 2.0, 2.6, 3.0, 3.5, 3.9, 4.1, 4.2, 5.0, 7.5, 10.0]
@@ -249,6 +264,10 @@ def divergence_survey(kp, torch, dev):
     return {"kappa_points": len(ks), "c_points": len(cs), "ms": ms, "grid_points_per_s": points / (ms * 1e-3),
             "quadrature_nodes": 192,
             "optimum_c": {str(pick[n]): float(copt[i]) for n, i in enumerate(idx)},
+            "optimum_c_refined": {str(pick[n]): float(c_ref[i]) for n, i in enumerate(idx)},
+            "refine_ms": opt_ms,
+            "refined_optimum_never_above_eq_c": bool(np.all(d_ref[dc_inside(ks)] <= dc_all(kp, kt)[dc_inside(ks)]
+                                                           * (1 + 1e-12))),
             "D_along_eq_c": {str(pick[n]): float(dc[i]) for n, i in enumerate(idx)},
             "dE_over_E_along_eq_c": {str(pick[n]): float(ec[i]) for n, i in enumerate(idx)},
             "kappa_where_optimum_c_leaves_the_range": [float(ks[i]) for i in np.nonzero(copt == cs[-1])[0][[0, -1]]]

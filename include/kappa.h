@@ -240,6 +240,24 @@ KAPPA_API kappa_status kappa_load_particles(const kappa_segment *segs, const kap
                                             uint64_t seed, int precision, void *px, void *py, void *pz, void *vx,
                                             void *vy, void *vz, void *stream);
 
+/* kappa_optimum_c -- the grid search of Sec. 3 that eq:c was fitted to, with
+ * a refinement: for each kappa_i, the c of c_grid (device array of nc values,
+ * ascending) with the smallest relative entropy D(f||g; kappa_i, c)
+ * (eq:relative_entropy, computed as in kappa_divergence_grid; NaN and negative
+ * grid entries skipped, lowest index on ties), then `iters` golden-section
+ * steps for the minimum of D between that point's grid neighbours (each step
+ * shrinks the bracket by 0.618).  c_opt[i] is the midpoint of the final
+ * bracket, or the grid point itself if D there is not larger; D_opt[i] (may be
+ * NULL) is D at c_opt[i].  D is unimodal in c on the paper's range, so the
+ * refinement finds the minimiser to about 1e-8 in c after 40 steps; where the
+ * optimum lies at an end of the grid (Fig. fig:map: past c = 1.5 just below
+ * kappa 4.1, at 0 just above) the result is that end.  kappa entries that are
+ * NaN or not above 3/2 give NaN (+INFINITY is the Maxwell limit).
+ * nk, nc <= 2^24, iters <= 200 (else KAPPA_ERANGE); 8-byte aligned arrays.
+ * Asynchronous. */
+KAPPA_API kappa_status kappa_optimum_c(const double *kappa, uint32_t nk, const double *c_grid, uint32_t nc,
+                                       uint32_t iters, double *c_opt, double *D_opt, void *stream);
+
 /* kappa_philox -- raw Philox4x32-10 blocks for particles counter_offset ..
  * counter_offset+n-1 of segment seg_id and draw number draw: out is a device
  * array of 4n uint32 words (r0, r1, r2, r3 per particle).  For bit-exact

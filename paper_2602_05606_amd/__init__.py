@@ -19,7 +19,7 @@ __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
     "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
-    "relative_entropy", "divergence_grid", "load_particles", "Cell",
+    "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell",
 ]
 
 
@@ -363,6 +363,24 @@ def divergence_grid(kappa, c=None, energy=True, argmin=False, device=None, strea
                                            _stream(stream, dev))
     _lib.check(st, "kappa_divergence_grid")
     return D, dE, am
+
+
+def optimum_c(kappa, c_grid, iters=40, device=None, stream=None):
+    """The c minimising D(f||g; kappa, c) for each kappa: the grid search of
+    Sec. 3 over c_grid (ascending), refined by golden-section steps between the
+    grid neighbours of the best point (kappa_optimum_c).  Returns (c_opt, D_opt)
+    as float64 device tensors of shape (nk,)."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else (
+        kappa.device if hasattr(kappa, "device") and kappa.is_cuda else torch.device("cuda"))
+    k = torch.as_tensor(kappa, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    cg = torch.as_tensor(c_grid, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    c_opt = torch.empty(k.numel(), dtype=torch.float64, device=dev)
+    d_opt = torch.empty(k.numel(), dtype=torch.float64, device=dev)
+    st = _lib.load().kappa_optimum_c(_ptr(k), k.numel(), _ptr(cg), cg.numel(), iters, _ptr(c_opt), _ptr(d_opt),
+                                     _stream(stream, dev))
+    _lib.check(st, "kappa_optimum_c")
+    return c_opt, d_opt
 
 
 def relative_entropy(kappa, counts, bin_width=0.2, eps=1e-10):

@@ -75,6 +75,7 @@ SIGNATURES = {
     "kappa_sample_exact_pareto": (_st, [_d, _d, _u64, _u64, _i, _vp, _vp, _vp, _vp, _vp]),
     "kappa_speed_histogram": (_st, [_vp, _vp, _vp, _u64, _i, _d, _d, _u32, _vp, _vp]),
     "kappa_divergence_grid": (_st, [_vp, _u32, _vp, _u32, _vp, _vp, _vp, _vp]),
+    "kappa_optimum_c": (_st, [_vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp]),
     "kappa_fill_probe": (_st, [_u64, _i, _vp, _vp, _vp, _vp]),
     "kappa_copy_probe": (_st, [_vp, _vp, _u64, _vp]),
     "kappa_status_string": (ctypes.c_char_p, [_i]),

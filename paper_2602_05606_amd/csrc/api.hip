@@ -315,6 +315,24 @@ kappa_status kappa_divergence_grid(const double *kappa, uint32_t nk, const doubl
                      "divergence kernel launch");
 }
 
+kappa_status kappa_optimum_c(const double *kappa, uint32_t nk, const double *c_grid, uint32_t nc, uint32_t iters,
+                             double *c_opt, double *D_opt, void *stream)
+{
+    if (nk > (1u << 24)) return fail(KAPPA_ERANGE, "nk %u above 2^24", nk);
+    if (nc > (1u << 24)) return fail(KAPPA_ERANGE, "nc %u above 2^24", nc);
+    if (iters > 200) return fail(KAPPA_ERANGE, "iters %u above 200", iters);
+    if (nk == 0) return KAPPA_OK;
+    if (nc == 0) return fail(KAPPA_EINVAL, "empty c grid");
+    if (!kappa || !c_grid || !c_opt) return fail(KAPPA_EINVAL, "null kappa, c_grid or c_opt");
+    auto mis = [](const void *p) { return p && reinterpret_cast<uintptr_t>(p) % 8 != 0; };
+    if (mis(kappa) || mis(c_grid) || mis(c_opt) || mis(D_opt))
+        return fail(KAPPA_EALIGN, "kappa, c_grid, c_opt and D_opt must be 8-byte aligned");
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_optimum(kappa, nk, c_grid, nc, iters, c_opt, D_opt, static_cast<hipStream_t>(stream)),
+                     "optimum kernel launch");
+}
+
 kappa_status kappa_fill_probe(uint64_t n, int precision, void *vx, void *vy, void *vz, void *stream)
 {
     if (precision != KAPPA_FP64 && precision != KAPPA_FP32)

@@ -106,6 +106,68 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// The c-independent part of every node for one kappa, in LDS.
+__device__ void build_nodes(DivNode *nodes, const KappaConst &s)
+{
+    if (!s.ok) return;
+    const double lnk = log(s.kappa);
+    for (int n = threadIdx.x; n < kDivNodes; n += blockDim.x) {
+        const double t = (n - kDivNeg) * kDivH;
+        const double ell = kHalfPi * sinh(t);
+        const double x = exp(ell);
+        // eq:kappax in logs; Maxwell: ln(2/sqrt(pi)) + ell/2 - x
+        const double lnf = s.maxwell ? 0.12078223763524522 + 0.5 * ell - x
+                                     : -lnk - s.lnB + 0.5 * (ell - lnk) - (s.kappa + 1.0) * log1p(x / s.kappa);
+        const double wf = kDivH * kHalfPi * cosh(t) * x * exp(lnf);  // h dx/dt f(x)
+        nodes[n] = DivNode{x, exp(-ell), lnf, wf, wf * x};
+    }
+}
+
+// D and the energy integral (before the 1/E_kappa factor) at one c, by the
+// calling wave: lanes over the nodes, then a butterfly sum, so every lane
+// returns the same two numbers.  Requires s.ok and a finite c >= 0.
+__device__ void wave_quality(const DivNode *nodes, const KappaConst &s, double c, double &dsum, double &esum)
+{
+    const int lane = threadIdx.x & 63;
+    const double kstar = s.kstar, inv_kstar = 1.0 / s.kstar;
+    const double a = s.a, b = s.b_over_c * c;
+    dsum = 0.0;
+    esum = 0.0;
+    for (int n = lane; n < kDivNodes; n += 64) {
+        const DivNode nd = nodes[n];
+        // f has underflowed (Maxwell: x > 745): the node adds nothing, and delta
+        // = ln g - ln f would be the difference of two numbers of order x
+        if (nd.w_d == 0.0) continue;
+        const double inv = 1.0 / (1.0 + c * nd.x);
+        const double t1 = nd.x * inv;                      // x / (1 + c x) <= 1/c
+        const double y = (a + b * nd.x) * t1;
+        // ln exp_q*(-y) = -kappa* log1p(y / kappa*), and ln of the (kappa*+1) power; -y for Maxwell
+        double lq, lq1;
+        if (s.maxwell) {
+            lq = -y;
+            lq1 = -y;
+        } else {
+            const double sl = log1p(y * inv_kstar);
+            lq = -kstar * sl;
+            lq1 = -(kstar + 1.0) * sl;
+        }
+        const double ln1mE = log(-expm1(lq));
+        const double yp = (a * nd.q + 2.0 * b + b * c * nd.x) * t1 * inv;
+        const double lng = 0.40546510810816438 + 0.5 * ln1mE + lq1 + log(yp);  // ln(3/2) + ...
+        double em1_minus_d, em1;
+        expm1_parts(lng - nd.lnf, em1_minus_d, em1);
+        dsum += nd.w_d * em1_minus_d;
+        esum += nd.w_e * em1;
+    }
+    dsum = wave_sum(dsum);
+    esum = wave_sum(esum);
+}
+
+__device__ inline double inv_energy(const KappaConst &s)
+{
+    return s.maxwell ? 2.0 / 3.0 : (2.0 * s.kappa - 3.0) / (3.0 * s.kappa);
+}
+
 __global__ void __launch_bounds__(256) divergence_kernel(const double *__restrict__ kappa,
                                                          const double *__restrict__ cvals, uint32_t nc,
                                                          double *__restrict__ D, double *__restrict__ dE)
@@ -113,67 +175,108 @@ __global__ void __launch_bounds__(256) divergence_kernel(const double *__restric
     __shared__ DivNode nodes[kDivNodes];
     const uint32_t i = blockIdx.y;
     const KappaConst s = kappa_const(kappa[i]);
-    if (s.ok) {
-        const double lnk = log(s.kappa);
-        for (int n = threadIdx.x; n < kDivNodes; n += blockDim.x) {
-            const double t = (n - kDivNeg) * kDivH;
-            const double ell = kHalfPi * sinh(t);
-            const double x = exp(ell);
-            // eq:kappax in logs; Maxwell: ln(2/sqrt(pi)) + ell/2 - x
-            const double lnf = s.maxwell ? 0.12078223763524522 + 0.5 * ell - x
-                                         : -lnk - s.lnB + 0.5 * (ell - lnk) - (s.kappa + 1.0) * log1p(x / s.kappa);
-            const double wf = kDivH * kHalfPi * cosh(t) * x * exp(lnf);  // h dx/dt f(x)
-            nodes[n] = DivNode{x, exp(-ell), lnf, wf, wf * x};
-        }
-    }
+    build_nodes(nodes, s);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const uint32_t j0 = blockIdx.x * kDivCPerBlock;
     const uint32_t j1 = j0 + kDivCPerBlock < nc ? j0 + kDivCPerBlock : nc;
-    const double kstar = s.kstar, inv_kstar = 1.0 / s.kstar;
-    const bool maxwell = s.maxwell;
     for (uint32_t j = j0 + wave; j < j1; j += nwaves) {
         const double c = cvals ? cvals[j] : (s.ok ? c_from_eq_c(s.kappa) : 0.0);
         double dsum = 0.0, esum = 0.0;
         const bool ok = s.ok && isfinite(c) && c >= 0.0;
-        if (ok) {
-            const double a = s.a, b = s.b_over_c * c;
-            for (int n = lane; n < kDivNodes; n += 64) {
-                const DivNode nd = nodes[n];
-                // f has underflowed (Maxwell: x > 745): the node adds nothing, and delta
-                // = ln g - ln f would be the difference of two numbers of order x
-                if (nd.w_d == 0.0) continue;
-                const double inv = 1.0 / (1.0 + c * nd.x);
-                const double t1 = nd.x * inv;                      // x / (1 + c x) <= 1/c
-                const double y = (a + b * nd.x) * t1;
-                // ln exp_q*(-y) = -kappa* log1p(y / kappa*), and ln of the (kappa*+1) power; -y for Maxwell
-                double lq, lq1;
-                if (maxwell) {
-                    lq = -y;
-                    lq1 = -y;
-                } else {
-                    const double sl = log1p(y * inv_kstar);
-                    lq = -kstar * sl;
-                    lq1 = -(kstar + 1.0) * sl;
-                }
-                const double ln1mE = log(-expm1(lq));
-                const double yp = (a * nd.q + 2.0 * b + b * c * nd.x) * t1 * inv;
-                const double lng = 0.40546510810816438 + 0.5 * ln1mE + lq1 + log(yp);  // ln(3/2) + ...
-                double em1_minus_d, em1;
-                expm1_parts(lng - nd.lnf, em1_minus_d, em1);
-                dsum += nd.w_d * em1_minus_d;
-                esum += nd.w_e * em1;
-            }
-        }
-        dsum = wave_sum(dsum);
-        esum = wave_sum(esum);
+        if (ok) wave_quality(nodes, s, c, dsum, esum);
         if (lane == 0) {
             const size_t o = static_cast<size_t>(i) * nc + j;
             const double nan = __builtin_nan("");
             D[o] = ok ? dsum : nan;
-            const double inv_energy = s.maxwell ? 2.0 / 3.0 : (2.0 * s.kappa - 3.0) / (3.0 * s.kappa);
-            if (dE) dE[o] = ok ? esum * inv_energy : nan;
+            if (dE) dE[o] = ok ? esum * inv_energy(s) : nan;
         }
+    }
+}
+
+// The grid search of Sec. 3 refined: for one kappa per block, the four waves
+// evaluate D at every c of the grid and keep the smallest (lowest index on
+// ties, NaN skipped); then wave 0 runs a golden-section search for the
+// minimum of D between the grid neighbours of that point (D is unimodal there
+// on the paper's range), `iters` steps, and writes the midpoint of the final
+// bracket and D there.
+__global__ void __launch_bounds__(256) optimum_kernel(const double *__restrict__ kappa,
+                                                      const double *__restrict__ cgrid, uint32_t nc, uint32_t iters,
+                                                      double *__restrict__ c_opt, double *__restrict__ D_opt)
+{
+    __shared__ DivNode nodes[kDivNodes];
+    __shared__ double best_d[4];
+    __shared__ uint32_t best_j[4];
+    const uint32_t i = blockIdx.x;
+    const KappaConst s = kappa_const(kappa[i]);
+    build_nodes(nodes, s);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    double bd = __builtin_inf();
+    uint32_t bj = 0xFFFFFFFFu;
+    if (s.ok) {
+        for (uint32_t j = wave; j < nc; j += nwaves) {
+            const double c = cgrid[j];
+            if (!(isfinite(c) && c >= 0.0)) continue;
+            double d, e;
+            wave_quality(nodes, s, c, d, e);
+            if (d < bd) {  // j increases within a wave: strict keeps the lowest index
+                bd = d;
+                bj = j;
+            }
+        }
+    }
+    if (lane == 0) {
+        best_d[wave] = bd;
+        best_j[wave] = bj;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    for (int w = 1; w < nwaves; ++w) {
+        if (best_d[w] < bd || (best_d[w] == bd && best_j[w] < bj)) {
+            bd = best_d[w];
+            bj = best_j[w];
+        }
+    }
+    const double nan = __builtin_nan("");
+    if (bj == 0xFFFFFFFFu) {
+        if (lane == 0) {
+            c_opt[i] = nan;
+            if (D_opt) D_opt[i] = nan;
+        }
+        return;
+    }
+    // bracket: the grid neighbours (clamped to the grid, and to valid c)
+    double lo = cgrid[bj > 0 ? bj - 1 : 0], hi = cgrid[bj + 1 < nc ? bj + 1 : nc - 1];
+    if (!(isfinite(lo) && lo >= 0.0)) lo = cgrid[bj];
+    if (!(isfinite(hi) && hi >= 0.0)) hi = cgrid[bj];
+    constexpr double kInvPhi = 0.6180339887498949;  // (sqrt(5) - 1) / 2
+    double x1 = hi - kInvPhi * (hi - lo), x2 = lo + kInvPhi * (hi - lo), f1, f2, e;
+    wave_quality(nodes, s, x1, f1, e);
+    wave_quality(nodes, s, x2, f2, e);
+    for (uint32_t it = 0; it < iters; ++it) {
+        if (f1 < f2) {
+            hi = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = hi - kInvPhi * (hi - lo);
+            wave_quality(nodes, s, x1, f1, e);
+        } else {
+            lo = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = lo + kInvPhi * (hi - lo);
+            wave_quality(nodes, s, x2, f2, e);
+        }
+    }
+    const double cm = 0.5 * (lo + hi);
+    double dm;
+    wave_quality(nodes, s, cm, dm, e);
+    // the grid point itself if the refinement did not beat it (a minimum at the end of the range)
+    const bool keep_grid = !(dm <= bd);
+    if (lane == 0) {
+        c_opt[i] = keep_grid ? cgrid[bj] : cm;
+        if (D_opt) D_opt[i] = keep_grid ? bd : dm;
     }
 }
 
@@ -206,6 +309,13 @@ __global__ void __launch_bounds__(64) argmin_kernel(const double *__restrict__ D
 }
 
 }  // namespace
+
+hipError_t launch_optimum(const double *kappa, uint32_t nk, const double *cgrid, uint32_t nc, uint32_t iters,
+                          double *c_opt, double *D_opt, hipStream_t stream)
+{
+    hipLaunchKernelGGL(optimum_kernel, dim3(nk), dim3(256), 0, stream, kappa, cgrid, nc, iters, c_opt, D_opt);
+    return hipGetLastError();
+}
 
 hipError_t launch_divergence(const double *kappa, uint32_t nk, const double *c, uint32_t nc, double *D, double *dE,
                              uint32_t *argmin, hipStream_t stream)

@@ -85,6 +85,8 @@ hipError_t launch_histogram(int mode, const void *vx, const void *vy, const void
                             uint32_t nbins, uint64_t *counts, hipStream_t stream);
 
 // ---- approximation quality over (kappa, c) ---------------------------------
+hipError_t launch_optimum(const double *kappa, uint32_t nk, const double *cgrid, uint32_t nc, uint32_t iters,
+                          double *c_opt, double *D_opt, hipStream_t stream);
 hipError_t launch_divergence(const double *kappa, uint32_t nk, const double *c, uint32_t nc, double *D, double *dE,
                              uint32_t *argmin, hipStream_t stream);
 

@@ -190,3 +190,14 @@ def test_pic_argument_checks():
     segs = (_lib.Segment * 1)()
     segs[0].kappa, segs[0].theta, segs[0].count = 3.0, 1.0, 10
     assert lib.kappa_load_particles(segs, None, 1, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+
+
+def test_optimum_argument_checks():
+    lib = _lib.load()
+    opt = lib.kappa_optimum_c
+    assert opt(FAKE, (1 << 24) + 1, FAKE, 10, 40, FAKE, None, None) == _lib.ERANGE
+    assert opt(FAKE, 4, FAKE, 10, 201, FAKE, None, None) == _lib.ERANGE
+    assert opt(FAKE, 4, FAKE, 0, 40, FAKE, None, None) == _lib.EINVAL
+    assert opt(FAKE, 4, None, 10, 40, FAKE, None, None) == _lib.EINVAL
+    assert opt(FAKE, 4, FAKE, 10, 40, ctypes.c_void_p(0x10004), None, None) == _lib.EALIGN
+    assert opt(None, 0, None, 0, 40, None, None, None) == _lib.OK
