@@ -202,6 +202,9 @@ KAPPA_API kappa_status kappa_plan_launch_pic(kappa_plan plan, void *px, void *py
 KAPPA_API kappa_status kappa_plan_graph_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx,
                                                    void *vy, void *vz, void *stream);
 
+/* kappa_plan_destroy -- waits for the plan's device (launches may still be in
+ * flight on any stream), then frees the plan's tables, cell table, captured
+ * graph and capture stream.  NULL is a no-op. */
 KAPPA_API kappa_status kappa_plan_destroy(kappa_plan plan);
 
 /* kappa_sample_batched -- many species and cells in one persistent launch:

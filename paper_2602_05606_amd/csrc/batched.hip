@@ -636,13 +636,32 @@ extern "C" kappa_status kappa_plan_graph_launch_pic_impl(kappa_plan p, void *px,
     return plan_graph_launch(p, Outputs{{vx, vy, vz}, {px, py, pz}}, stream);
 }
 
+namespace kappa {
+namespace {
+// Makes the plan's device current for the lifetime of the guard.
+struct PlanDevice {
+    int prev = -1;
+    explicit PlanDevice(const kappa_plan_s *p)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != p->device) (void)hipSetDevice(p->device);
+    }
+    ~PlanDevice()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+}  // namespace kappa
+
 extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell *cells)
 {
+    PlanDevice guard(p);
     if (p->cell_block) {
-        // a captured graph may still read the old table
-        drop_graph(p);
+        // launches in flight, or the captured graph, may still read the old table
         kappa_status st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
         if (st != KAPPA_OK) return st;
+        drop_graph(p);
         hipFree(p->cell_block);
         p->cell_block = nullptr;
         p->cell32 = nullptr;
@@ -770,6 +789,9 @@ extern "C" kappa_status kappa_plan_total_impl(kappa_plan p, uint64_t *total)
 
 extern "C" kappa_status kappa_plan_destroy_impl(kappa_plan p)
 {
+    PlanDevice guard(p);
+    // launches of this plan may still be in flight on any stream
+    (void)hipDeviceSynchronize();
     drop_graph(p);
     if (p->capture_stream) hipStreamDestroy(p->capture_stream);
     if (p->dev_block) hipFree(p->dev_block);
