@@ -9,8 +9,9 @@
 // these IEEE operations gets the same counts.
 //
 // Each block keeps one sub-histogram per wave in LDS (fewer atomic
-// collisions), walks the arrays with a grid stride, and adds its counts to the
-// caller's uint64 counters with one atomic per bin at the end.
+// collisions), walks the arrays with a grid stride (16-byte loads when the
+// arrays are 16-byte aligned), and adds its counts to the caller's uint64
+// counters with one atomic per bin at the end.
 #include "kappa_internal.hpp"
 
 namespace kappa {
@@ -20,7 +21,34 @@ namespace {
 constexpr int kHistBlock = 256;
 constexpr int kHistWaves = kHistBlock / 64;
 
+// Bin of one squared speed: an estimate from sqrt, then the exact decision
+// against the squared edges.
 template <typename T>
+__device__ __forceinline__ uint32_t bin_of(T s2, const T *edge2, T inv_w, uint32_t nbins)
+{
+    const T est = sqrt(s2) * inv_w;
+    uint32_t k = est < static_cast<T>(nbins) ? static_cast<uint32_t>(est) : nbins;
+    while (k > 0 && s2 < edge2[k]) --k;
+    while (k < nbins && s2 >= edge2[k + 1]) ++k;
+    return k;
+}
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+
+// VEC: 16-byte loads of Vec<T>::n particles per array (outputs 16-byte
+// aligned); otherwise one particle per load.  The counts do not depend on it.
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(kHistBlock) histogram_kernel(const T *vx, const T *vy, const T *vz, uint64_t n,
                                                                double width, uint32_t nbins,
                                                                unsigned long long *counts)
@@ -38,15 +66,36 @@ __global__ void __launch_bounds__(kHistBlock) histogram_kernel(const T *vx, cons
     uint32_t *mine = bins + (threadIdx.x >> 6) * nb;
     const T inv_w = static_cast<T>(1.0 / width);
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride) {
-        const T x = vx[j], y = vy[j], z = vz[j];
-        const T s2 = (x * x + y * y) + z * z;
-        // estimate, then settle on the exact bin against the squared edges
-        const T est = sqrt(s2) * inv_w;
-        uint32_t k = est < static_cast<T>(nbins) ? static_cast<uint32_t>(est) : nbins;
-        while (k > 0 && s2 < edge2[k]) --k;
-        while (k < nbins && s2 >= edge2[k + 1]) ++k;
-        atomicAdd(&mine[k], 1u);
+    const uint64_t first = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if constexpr (VEC) {
+        using V = typename Vec<T>::type;
+        constexpr int W = Vec<T>::n;
+        const uint64_t ngroups = n / W;
+        for (uint64_t g = first; g < ngroups; g += stride) {
+            const V x = reinterpret_cast<const V *>(vx)[g];
+            const V y = reinterpret_cast<const V *>(vy)[g];
+            const V z = reinterpret_cast<const V *>(vz)[g];
+            T xs[W], ys[W], zs[W];
+            __builtin_memcpy(xs, &x, sizeof(V));
+            __builtin_memcpy(ys, &y, sizeof(V));
+            __builtin_memcpy(zs, &z, sizeof(V));
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const T s2 = (xs[k] * xs[k] + ys[k] * ys[k]) + zs[k] * zs[k];
+                atomicAdd(&mine[bin_of(s2, edge2, inv_w, nbins)], 1u);
+            }
+        }
+        // the ragged tail (fewer than W particles)
+        for (uint64_t j = ngroups * W + first; j < n; j += stride) {
+            const T s2 = (vx[j] * vx[j] + vy[j] * vy[j]) + vz[j] * vz[j];
+            atomicAdd(&mine[bin_of(s2, edge2, inv_w, nbins)], 1u);
+        }
+    } else {
+        for (uint64_t j = first; j < n; j += stride) {
+            const T x = vx[j], y = vy[j], z = vz[j];
+            const T s2 = (x * x + y * y) + z * z;
+            atomicAdd(&mine[bin_of(s2, edge2, inv_w, nbins)], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < nb; k += kHistBlock) {
@@ -72,14 +121,27 @@ hipError_t launch_histogram(int mode, const void *vx, const void *vy, const void
     const int grid = static_cast<int>(need < cap ? (need > 0 ? need : 1) : cap);
     const size_t lds = histogram_lds_bytes(mode, nbins);
     auto *c = reinterpret_cast<unsigned long long *>(counts);
-    if (mode == kModeF64)
-        hipLaunchKernelGGL(histogram_kernel<double>, dim3(grid), dim3(kHistBlock), lds, stream,
-                           static_cast<const double *>(vx), static_cast<const double *>(vy),
-                           static_cast<const double *>(vz), n, width, nbins, c);
-    else
-        hipLaunchKernelGGL(histogram_kernel<float>, dim3(grid), dim3(kHistBlock), lds, stream,
-                           static_cast<const float *>(vx), static_cast<const float *>(vy),
-                           static_cast<const float *>(vz), n, width, nbins, c);
+    auto a16 = [](const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+    const bool vec = a16(vx) && a16(vy) && a16(vz);
+    if (mode == kModeF64) {
+        auto *x = static_cast<const double *>(vx), *y = static_cast<const double *>(vy),
+             *z = static_cast<const double *>(vz);
+        if (vec)
+            hipLaunchKernelGGL((histogram_kernel<double, true>), dim3(grid), dim3(kHistBlock), lds, stream, x, y, z, n,
+                               width, nbins, c);
+        else
+            hipLaunchKernelGGL((histogram_kernel<double, false>), dim3(grid), dim3(kHistBlock), lds, stream, x, y, z,
+                               n, width, nbins, c);
+    } else {
+        auto *x = static_cast<const float *>(vx), *y = static_cast<const float *>(vy),
+             *z = static_cast<const float *>(vz);
+        if (vec)
+            hipLaunchKernelGGL((histogram_kernel<float, true>), dim3(grid), dim3(kHistBlock), lds, stream, x, y, z, n,
+                               width, nbins, c);
+        else
+            hipLaunchKernelGGL((histogram_kernel<float, false>), dim3(grid), dim3(kHistBlock), lds, stream, x, y, z,
+                               n, width, nbins, c);
+    }
     return hipGetLastError();
 }
 

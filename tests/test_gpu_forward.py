@@ -112,6 +112,28 @@ def test_c2_full_size_sampled(orc, kappa, precision):
     assert all(bool(torch.isfinite(t).all()) for t in v)
 
 
+def test_beyond_2_to_31_particles_in_one_call(orc):
+    """One FP32 call of 2^31 + 1029 particles (25.8 GB of outputs): indices past
+    2^31 and the last group (ragged) must match the oracle, and the launch must
+    cover every particle (no 32-bit index wrap)."""
+    n = (1 << 31) + 1029
+    vx, vy, vz = (torch.full((n,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(3))
+    kp.sample(2.5, 1.1, n, 13, precision=kp.FP32, out=(vx, vy, vz))
+    torch.cuda.synchronize()
+    try:
+        assert bool(torch.isfinite(vx).all()) and bool(torch.isfinite(vz).all())
+        rng = np.random.default_rng(31)
+        idx = np.concatenate([rng.integers(0, n, 4000), np.arange((1 << 31) - 8, (1 << 31) + 8),
+                              np.arange(n - 12, n)]).astype(np.uint64)
+        it = torch.from_numpy(idx.astype(np.int64)).cuda()
+        g = to_host(vx[it], vy[it], vz[it])
+        r = orc.sample_indices(2.5, 1.1, idx, 13, mode=1)
+        assert norm_rel_err(g, r) <= TOL_FP32
+    finally:
+        del vx, vy, vz
+        torch.cuda.empty_cache()
+
+
 def test_determinism_and_chunking():
     n = 3_000_001
     for precision in (kp.FP64, kp.FP32):
