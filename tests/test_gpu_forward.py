@@ -61,6 +61,20 @@ def test_forward_parity_ragged(orc, kappa, precision):
     assert err <= tol
 
 
+@pytest.mark.parametrize("kappa,theta", [(1.5 + 1e-9, 1e-3), (1.5 + 1e-6, 1.0), (1e4, 1e3), (1e8, 0.5),
+                                         (1e12, 1.0), (3.0, 1e-30), (3.0, 1e30)])
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
+def test_degenerate_kappa_and_theta(orc, kappa, theta, precision):
+    """kappa just above 3/2 (kappa* -> 1, the heaviest tail eq:kappa allows),
+    very large kappa (kappa* huge: z = -lT/kappa* tiny), and theta far from 1."""
+    n = 200_003
+    g = to_host(*gpu_sample(kappa, theta, n, 29, precision))
+    r = orc.sample(kappa, theta, n, 29, mode=MODE[precision])[:3]
+    err = norm_rel_err(g, r)
+    print(f"kappa {kappa} theta {theta} precision {precision}: max error {err:.3e}")
+    assert err <= (TOL_FP64 if precision == kp.FP64 else TOL_FP32)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 63, 64, 65, 1023, 4097])
 def test_small_and_ragged_sizes(orc, n):
     for precision in (kp.FP64, kp.FP32):
