@@ -13,7 +13,9 @@
  *
  *   kappa    Kappa index; the distribution needs kappa > 3/2 (Sec. 2).  The
  *            fitted parameter c of eq:c covers kappa in [1.5, 10] (Sec. 3);
- *            larger values are accepted.  kappa <= 3/2, NaN or Inf: KAPPA_EINVAL.
+ *            larger values are accepted.  +INFINITY is the Maxwell limit
+ *            where an entry point says so (see kappa_params).  kappa <= 3/2,
+ *            NaN, or +INFINITY elsewhere: KAPPA_EINVAL.
  *   theta    most probable speed, > 0 and finite, else KAPPA_EINVAL.
  *   seed     64-bit Philox4x32-10 key: key = (low 32 bits, high 32 bits).
  *   counters particle i of segment seg draws the Philox4x32-10 block with
