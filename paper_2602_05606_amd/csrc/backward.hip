@@ -82,7 +82,21 @@ __device__ __forceinline__ float dL_dkappa_f32(const InvF32 &inv)
     return z < 0.5f ? z * z * p : fmaf(z, inv.ez, -inv.em1);
 }
 
-template <int MODE, int U, bool VEC>
+// The generator's Philox block of particle counter_offset + j (as in the
+// forward kernel: with HI_UNIFORM the launch's counters share their high word,
+// taken from the kernel argument so that the first rounds run partly on the
+// scalar unit; the words are the same).
+template <bool HI_UNIFORM>
+__device__ __forceinline__ Block4 bwd_block(const BwdArgs &a, uint64_t j)
+{
+    if constexpr (HI_UNIFORM)
+        return philox4x32_10(static_cast<uint32_t>(a.counter_offset) + static_cast<uint32_t>(j),
+                             static_cast<uint32_t>(a.counter_offset >> 32), a.seg, 0, a.k0, a.k1);
+    else
+        return particle_block(a.counter_offset + j, a.seg, 0, a.k0, a.k1);
+}
+
+template <int MODE, int U, bool VEC, bool HI_UNIFORM>
 __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
 {
     using T = typename std::conditional<MODE == kModeF64, double, float>::type;
@@ -114,7 +128,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             tail_dot[k] = 0.0f;
-            const Block4 b = particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+            const Block4 b = bwd_block<HI_UNIFORM>(a, j0 + k);
             if constexpr (MODE == kModeF64) {
                 bool high;
                 double u;
@@ -225,16 +239,23 @@ constexpr int unroll_for(int mode)
     return mode == kModeF64 ? 2 : 4;
 }
 
-template <int MODE>
+template <int MODE, bool HI_UNIFORM>
 hipError_t launch_mode(const BwdArgs &a, bool vec, hipStream_t stream)
 {
     constexpr int U = unroll_for(MODE);
     const int grid = backward_grid(a.n);
     if (vec)
-        hipLaunchKernelGGL((backward_kernel<MODE, U, true>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
+        hipLaunchKernelGGL((backward_kernel<MODE, U, true, HI_UNIFORM>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
     else
-        hipLaunchKernelGGL((backward_kernel<MODE, U, false>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
+        hipLaunchKernelGGL((backward_kernel<MODE, U, false, HI_UNIFORM>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
     return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(const BwdArgs &a, bool vec, hipStream_t stream)
+{
+    const bool uniform_hi = a.n == 0 || (a.counter_offset >> 32) == ((a.counter_offset + a.n - 1) >> 32);
+    return uniform_hi ? launch_mode<MODE, true>(a, vec, stream) : launch_mode<MODE, false>(a, vec, stream);
 }
 
 }  // namespace
