@@ -11,7 +11,10 @@ Each pin ties the oracle to something other than itself:
   speeds of the C oracle (a route that never evaluates g);
 * the grid-search statements of Sec. 3 (Fig. fig:map): the optimum c sits on
   eq:c in the fitted ranges, runs off the top of the c range just below
-  kappa 4.1 and drops to zero just above it.
+  kappa 4.1 and drops to zero just above it;
+* the tail-energy argument at kappa 4.1 (about 1% of the particles above
+  v = 3 theta missing, 19% of the energy there, so 0.19% of it lost), with
+  the tails of eq:CDF and eq:CDF_E from scipy's incomplete beta function.
 A mutation test plants mistakes in the oracle and checks that a pin fails.
 """
 import json
@@ -106,6 +109,32 @@ def test_grid_search_statements():
     assert D(4.2, 0.0) < D(4.2, 0.05)
     # the fit anchor (4.1, 0.4) is not the optimum there: c has little effect near 4.1
     assert abs(D(4.1, 0.4) / D(4.1, 0.0) - 1) < 0.5
+
+
+def test_tail_energy_argument_at_kappa_4p1():
+    """Sec. 3, discussion of fig:DE(b): at kappa 4.1 the approximation puts
+    about 1% too few particles above v = 3 theta (x = 9); eq:CDF_E says that
+    tail carries about 19% of the energy, so about 0.19% of the energy goes
+    missing, in line with the 10^-2.5 energy error there.  Each step is
+    checked against the exact beta-prime tails, not the oracle's own f."""
+    st = GOLD["energy_tail_fraction_v_gt_3theta_kappa_4p1"]
+    k, x0 = st["kappa"], st["x"]
+    pop_kappa = special.betaincc(1.5, k - 0.5, x0 / (x0 + k))     # eq:CDF
+    energy_kappa = special.betaincc(2.5, k - 1.5, x0 / (x0 + k))  # eq:CDF_E
+    assert round(energy_kappa, 2) == st["approx"]
+    with mp.workdps(Q.DPS):
+        p = Q.Params(k)
+        pop_approx = float(Q.G_complement(mp.mpf(x0), p))
+        e_kappa = 3 * k / (2 * k - 3)  # mean x of the Kappa distribution, eq:kappaE
+        tail_approx = float(mp.quad(lambda x: x * Q.g_pdf(x, p), [x0, 30, 100, 1000, mp.inf])) / e_kappa
+    lost_population = 1 - pop_approx / pop_kappa
+    assert 0.005 < lost_population < 0.02          # "1% of the tail population"
+    lost_energy = energy_kappa - tail_approx
+    assert 0.0015 < lost_energy < 0.0025           # "0.19% of the energy density"
+    assert abs(lost_energy - lost_population * energy_kappa) < 0.0005
+    # the whole energy error at 4.1 is of order 10^-2.5 (fig:DE(b))
+    de = abs(float(Q.energy_error(k)))
+    assert abs(math.log10(de) - GOLD["energy_error_at_transition"]["log10_approx"]) < 0.25
 
 
 def test_paper_level_along_eq_c():

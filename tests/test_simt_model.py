@@ -25,6 +25,9 @@ def test_acceptance_ranges():
     assert np.all(np.diff(p1) > 0)
     assert abs(p2[0] - r2["high"]) < 0.005 and abs(p2[-1] - r2["low"]) < 0.005
     assert np.all(np.diff(p2) < 0)
+    # the rejection rate 1 - p2 spans the range Sec. 6 prints
+    r3 = GOLD["pareto_rejection_range"]
+    assert abs((1 - p2[0]) - r3["low"]) < 0.005 and abs((1 - p2[-1]) - r3["high"]) < 0.005
 
 
 def _max_of_geometric(rho, t, kmax=400):
