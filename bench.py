@@ -32,7 +32,8 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_forward_fp32_c2.json")
 # instruction occupies a SIMD for 2 cycles (the 157.3 TFLOP/s FP32 vector
 # peak); transcendentals and 32x32->64 integer multiplies run at a quarter of
 # that rate (8 cycles; measured 8.9 on the chip).
-SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9
+SIMD_COUNT = 256 * 4
+SIMD_CYCLES_PER_S = SIMD_COUNT * 2.4e9
 CYCLES_FULL, CYCLES_QUARTER = 2, 8
 
 
@@ -62,10 +63,13 @@ def measured_traffic(launch_bytes):
             "algorithmic_bytes": launch_bytes, "calibration": t.get("calibration")}
 
 
-def alu_roofline(particles_per_s):
+def alu_roofline(particles_per_s, clock=None):
     """VALU-issue roofline of the dominant kernel from its measured instruction
     counts (rocprofv3 SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32 and the static
-    v_mad_u64_u32 count), or None when they were taken on other kernel sources."""
+    v_mad_u64_u32 count), or None when they were taken on other kernel sources.
+    The peak is the 2.4 GHz one; with `clock` (the core clock measured by the
+    clock probe during the same workload) the fraction of the issue capacity
+    at that clock is added."""
     try:
         with open(VALU_FILE) as f:
             v = json.load(f)
@@ -77,9 +81,39 @@ def alu_roofline(particles_per_s):
     full = v["valu_per_particle"] - quarter
     cycles_per_particle = (CYCLES_FULL * full + CYCLES_QUARTER * quarter) / 64.0
     achieved = particles_per_s * cycles_per_particle
-    return {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
-            "frac": achieved / SIMD_CYCLES_PER_S, "valu_per_particle": v["valu_per_particle"],
-            "quarter_rate_per_particle": quarter, "simd_cycles_per_particle": cycles_per_particle}
+    out = {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
+           "frac": achieved / SIMD_CYCLES_PER_S, "valu_per_particle": v["valu_per_particle"],
+           "quarter_rate_per_particle": quarter, "simd_cycles_per_particle": cycles_per_particle}
+    if clock:
+        at_clock = SIMD_COUNT * clock["core_clock_ghz"] * 1e9
+        out.update({"measured_clock": clock, "peak_at_measured_clock": at_clock,
+                    "frac_at_measured_clock": achieved / at_clock})
+    return out
+
+
+def measure_clock(kp, torch, kappas, theta, n, seed, out, avg_kernel_ms):
+    """Core clock during the timed workload: one clock-probe launch per kappa
+    right after the timed steps (the same kernel with per-workgroup stamps of
+    the core-clock and constant-rate counters), weighted by wave lifetime.
+    The launches run back to back like the timed ones, into stamp buffers
+    allocated beforehand."""
+    bufs = [torch.empty(kp.clock_probe_stamps(n), dtype=torch.int64, device=out[0].device) for _ in kappas]
+    kp.clock_probe(kappas[0], theta, n, seed, precision=kp.FP32, out=out, stamps=bufs[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    runs = [kp.clock_probe(k, theta, n, seed, precision=kp.FP32, out=out, stamps=b) for k, b in zip(kappas, bufs)]
+    e1.record()
+    torch.cuda.synchronize()
+    cycles = ticks = 0
+    for _, stamps, hz in runs:
+        s = stamps.cpu()
+        cycles += int((s[:, 2] - s[:, 0]).sum())
+        ticks += int((s[:, 3] - s[:, 1]).sum())
+    ghz = cycles / ticks * hz / 1e9
+    return {"core_clock_ghz": ghz, "max_clock_ghz": 2.4, "constant_rate_counter_hz": hz,
+            "probe_launch_ms": e0.elapsed_time(e1) / len(kappas), "timed_launch_ms": avg_kernel_ms,
+            "how": "kappa_clock_probe: the forward kernel with core-clock (s_memtime) and constant-rate "
+                   "(s_memrealtime) stamps per workgroup, one launch per kappa after the timed steps"}
 
 
 def time_launches(fn, reps, torch, warm=2):
@@ -404,8 +438,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
                      "kernel": "forward_kernel<FP32 tail, 4 particles/thread>",
                      "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
-        "roofline_alu": alu_roofline(n / (avg_kernel_ms * 1e-3)),
     }
+    clock = measure_clock(kp, torch, kappas, theta, n, seed, out32, avg_kernel_ms)
+    log(f"core clock during the workload: {clock['core_clock_ghz']:.3f} GHz "
+        f"(probe launch {clock['probe_launch_ms']:.4f} ms against {avg_kernel_ms:.4f} ms timed)")
+    result["roofline_alu"] = alu_roofline(n / (avg_kernel_ms * 1e-3), clock)
 
     if args.calibrate:
         src = torch.empty(300_000_000, dtype=torch.float32, device=dev)

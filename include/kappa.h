@@ -345,6 +345,29 @@ KAPPA_API kappa_status kappa_divergence_grid(const double *kappa, uint32_t nk, c
 KAPPA_API kappa_status kappa_fill_probe(uint64_t n, int precision, void *vx, void *vy, void *vz, void *stream);
 KAPPA_API kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t bytes, void *stream);
 
+/* kappa_clock_probe: kappa_sample (same arguments, same outputs, same kernel
+ * and launch shape) with timestamps, to find the core clock the chip holds
+ * while it runs the generator.  Thread 0 of workgroup w writes
+ *   stamps[4w + 0], stamps[4w + 2]: shader-clock counter (core clock cycles)
+ *                                   at entry and exit of its wave;
+ *   stamps[4w + 1], stamps[4w + 3]: constant-rate counter at the same points,
+ *                                   ticking at *wall_hz (written, host).
+ * (stamps[4w+2] - stamps[4w]) / (stamps[4w+3] - stamps[4w+1]) * *wall_hz is
+ * that wave's mean core clock in Hz.
+ *   stamps      device array of stamps_len uint64, 8-byte aligned; written
+ *               for w < *blocks.
+ *   blocks      host; written with the number of workgroups of the launch
+ *               (also when stamps_len is too small: then KAPPA_ERANGE).
+ *               4 * ceil(n / 64) entries always suffice.
+ * The outputs must be 16-byte aligned (KAPPA_EALIGN otherwise) and the
+ * launch shape the default one (KAPPA_EINVAL when KAPPA_FORWARD_SHAPE
+ * changes the particles per thread).  n = 0 writes *blocks = 0 and launches
+ * nothing.  Asynchronous like kappa_sample. */
+KAPPA_API kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed,
+                                         uint64_t counter_offset, uint32_t seg_id, int precision, void *vx, void *vy,
+                                         void *vz, uint64_t *stamps, uint64_t stamps_len, uint32_t *blocks,
+                                         double *wall_hz, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 KAPPA_API const char *kappa_status_string(kappa_status status);
 

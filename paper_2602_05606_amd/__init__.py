@@ -18,7 +18,7 @@ from ._lib import FP32, FP32_NOTAIL, FP64, Cell, KappaError, Segment
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
-    "fill_probe", "copy_probe", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
+    "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
     "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell",
 ]
 
@@ -326,6 +326,42 @@ def copy_probe(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     _lib.check(_lib.load().kappa_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)),
                "kappa_copy_probe")
+
+
+def clock_probe(kappa, theta, n, seed, *, counter_offset=0, seg_id=0, precision=FP32, out=None, device=None,
+                stamps=None, stream=None):
+    """sample() through kappa_clock_probe: the same outputs from the same
+    kernel, plus per-workgroup clock stamps.  Returns ((vx, vy, vz), stamps,
+    wall_hz) with stamps an int64 device tensor of shape (workgroups, 4):
+    shader-clock counter at entry, constant-rate counter at entry, the same
+    two at exit; the constant-rate counter ticks at wall_hz.  `stamps` may
+    bring a contiguous int64 device buffer (clock_probe_stamps(n) entries)."""
+    torch = _torch()
+    vx, vy, vz = _outputs(n, precision, out, device)
+    if stamps is None:
+        stamps = torch.empty(clock_probe_stamps(n), dtype=torch.int64, device=vx.device)
+    elif stamps.dtype != torch.int64 or not stamps.is_contiguous():
+        raise ValueError("stamps must be a contiguous int64 device tensor")
+    blocks, hz = ctypes.c_uint32(0), ctypes.c_double(0.0)
+    st = _lib.load().kappa_clock_probe(float(kappa), float(theta), n, seed, counter_offset, seg_id, precision,
+                                       _ptr(vx), _ptr(vy), _ptr(vz), _ptr(stamps), stamps.numel(),
+                                       ctypes.byref(blocks), ctypes.byref(hz), _stream(stream, vx.device))
+    _lib.check(st, "kappa_clock_probe")
+    return (vx, vy, vz), stamps[:4 * blocks.value].view(blocks.value, 4), hz.value
+
+
+def clock_probe_stamps(n):
+    """Entries of a stamps buffer that suffices for clock_probe of n particles."""
+    return 4 * max(1, -(-n // 64))
+
+
+def core_clock_hz(stamps, wall_hz):
+    """Mean core clock (Hz) over the waves stamped by clock_probe, each weighted
+    by its duration: total core cycles over total constant-rate time."""
+    s = stamps.cpu()
+    cycles = int((s[:, 2] - s[:, 0]).sum())  # differences in int64: the counters run from boot
+    ticks = int((s[:, 3] - s[:, 1]).sum())
+    return cycles / ticks * wall_hz if ticks > 0 else float("nan")
 
 
 def speed_histogram(vx, vy, vz, theta, bin_width=0.2, nbins=100, counts=None, stream=None):

@@ -79,6 +79,24 @@ bool vec_aligned(int precision, const void *vx, const void *vy, const void *vz)
            reinterpret_cast<uintptr_t>(vz) % 16 == 0;
 }
 
+FwdArgs forward_args(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id,
+                     void *vx, void *vy, void *vz)
+{
+    const Setup s = make_setup(kappa);
+    FwdArgs a;
+    a.n = n;
+    a.counter_offset = counter_offset;
+    a.seg = seg_id;
+    a.k0 = static_cast<uint32_t>(seed);
+    a.k1 = static_cast<uint32_t>(seed >> 32);
+    a.vx = vx;
+    a.vy = vy;
+    a.vz = vz;
+    a.s64 = species_f64(s, theta);
+    a.s32 = species_f32(s, theta);
+    return a;
+}
+
 }  // namespace
 
 kappa_status fail(kappa_status status, const char *fmt, ...)
@@ -162,21 +180,49 @@ kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed,
     if (st != KAPPA_OK || n == 0) return st;
     st = require_device();
     if (st != KAPPA_OK) return st;
-    const Setup s = make_setup(kappa);
-    FwdArgs a;
-    a.n = n;
-    a.counter_offset = counter_offset;
-    a.seg = seg_id;
-    a.k0 = static_cast<uint32_t>(seed);
-    a.k1 = static_cast<uint32_t>(seed >> 32);
-    a.vx = vx;
-    a.vy = vy;
-    a.vz = vz;
-    a.s64 = species_f64(s, theta);
-    a.s32 = species_f32(s, theta);
+    const FwdArgs a = forward_args(kappa, theta, n, seed, counter_offset, seg_id, vx, vy, vz);
     const bool vec = vec_aligned(precision, vx, vy, vz);
     const Shape shape = forward_shape(precision, n, vec);
     return check_hip(launch_forward(precision, shape, vec, a, static_cast<hipStream_t>(stream)), "forward kernel launch");
+}
+
+kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                               uint32_t seg_id, int precision, void *vx, void *vy, void *vz, uint64_t *stamps,
+                               uint64_t stamps_len, uint32_t *blocks, double *wall_hz, void *stream)
+{
+    if (!blocks || !wall_hz) return fail(KAPPA_EINVAL, "null blocks or wall_hz pointer");
+    *blocks = 0;
+    *wall_hz = 0.0;
+    if (!kappa_or_maxwell_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be > 3/2 or +inf (got %g)", kappa);
+    if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (n > 0 && counter_offset > UINT64_MAX - (n - 1))
+        return fail(KAPPA_EINVAL, "counter_offset + n exceeds 2^64");
+    kappa_status st = check_outputs(n, precision, vx, vy, vz);
+    if (st != KAPPA_OK || n == 0) return st;
+    if (!vec_aligned(precision, vx, vy, vz))
+        return fail(KAPPA_EALIGN, "the clock probe times the vector-store kernel: outputs must be 16-byte aligned");
+    if (!stamps) return fail(KAPPA_EINVAL, "null stamps pointer");
+    if (reinterpret_cast<uintptr_t>(stamps) % 8) return fail(KAPPA_EALIGN, "stamps must be 8-byte aligned");
+    const Shape shape = forward_shape(precision, n, true);
+    if (shape.unroll != forward_default_unroll(precision))
+        return fail(KAPPA_EINVAL, "the clock probe times the default shape (KAPPA_FORWARD_SHAPE overrides the unroll)");
+    *blocks = static_cast<uint32_t>(shape.grid);
+    if (stamps_len / 4 < static_cast<uint64_t>(shape.grid))
+        return fail(KAPPA_ERANGE, "stamps holds %llu entries, the launch needs 4 x %d",
+                    (unsigned long long)stamps_len, shape.grid);
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    int dev = 0, khz = 0;
+    st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != KAPPA_OK) return st;
+    st = check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+    if (st != KAPPA_OK) return st;
+    if (khz <= 0) return fail(KAPPA_EDEVICE, "device reports no constant-rate counter");
+    *wall_hz = 1e3 * khz;
+    const FwdArgs a = forward_args(kappa, theta, n, seed, counter_offset, seg_id, vx, vy, vz);
+    return check_hip(launch_forward_clock(precision, shape, a, stamps, static_cast<hipStream_t>(stream)),
+                     "clock probe launch");
 }
 
 size_t kappa_backward_workspace_bytes(uint64_t n)

@@ -52,10 +52,24 @@ __device__ __forceinline__ Block4 fwd_block(const FwdArgs &a, uint64_t j)
         return particle_block(a.counter_offset + j, a.seg, 0, a.k0, a.k1);
 }
 
-template <int MODE, int U, bool HI_UNIFORM>
-__global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
+// CLOCK = true is the clock probe's instantiation: the same kernel, plus
+// per-workgroup stamps of the shader-clock counter (s_memtime, core clock
+// cycles) and the constant-rate counter (s_memrealtime) at entry and exit of
+// wave 0, written by its thread 0 to stamps[4w .. 4w+3] for workgroup w.
+// Product launches instantiate CLOCK = false and pass no stamps.
+template <int MODE, int U, bool HI_UNIFORM, bool CLOCK>
+__global__ void __launch_bounds__(256) forward_kernel(FwdArgs a, uint64_t *stamps)
 {
     using T = typename std::conditional<MODE == kModeF64, double, float>::type;
+    if constexpr (CLOCK) {
+        // stored at once, so that no registers are held across the kernel
+        const uint64_t clk0 = __builtin_amdgcn_s_memtime();
+        const uint64_t rt0 = __builtin_amdgcn_s_memrealtime();
+        if (threadIdx.x == 0) {
+            stamps[4 * static_cast<uint64_t>(blockIdx.x)] = clk0;
+            stamps[4 * static_cast<uint64_t>(blockIdx.x) + 1] = rt0;
+        }
+    }
     T *vx = static_cast<T *>(a.vx);
     T *vy = static_cast<T *>(a.vy);
     T *vz = static_cast<T *>(a.vz);
@@ -101,6 +115,14 @@ __global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
             }
         }
     }
+    if constexpr (CLOCK) {
+        const uint64_t clk1 = __builtin_amdgcn_s_memtime();
+        const uint64_t rt1 = __builtin_amdgcn_s_memrealtime();
+        if (threadIdx.x == 0) {
+            stamps[4 * static_cast<uint64_t>(blockIdx.x) + 2] = clk1;
+            stamps[4 * static_cast<uint64_t>(blockIdx.x) + 3] = rt1;
+        }
+    }
 }
 
 namespace {
@@ -110,10 +132,10 @@ hipError_t launch_mode(const Shape &sh, const FwdArgs &a, hipStream_t stream)
 {
     dim3 grid(sh.grid), block(sh.block);
     switch (sh.unroll) {
-    case 1: hipLaunchKernelGGL((forward_kernel<MODE, 1, HI_UNIFORM>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((forward_kernel<MODE, 2, HI_UNIFORM>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((forward_kernel<MODE, 4, HI_UNIFORM>), grid, block, 0, stream, a); break;
-    case 8: hipLaunchKernelGGL((forward_kernel<MODE, 8, HI_UNIFORM>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((forward_kernel<MODE, 1, HI_UNIFORM, false>), grid, block, 0, stream, a, nullptr); break;
+    case 2: hipLaunchKernelGGL((forward_kernel<MODE, 2, HI_UNIFORM, false>), grid, block, 0, stream, a, nullptr); break;
+    case 4: hipLaunchKernelGGL((forward_kernel<MODE, 4, HI_UNIFORM, false>), grid, block, 0, stream, a, nullptr); break;
+    case 8: hipLaunchKernelGGL((forward_kernel<MODE, 8, HI_UNIFORM, false>), grid, block, 0, stream, a, nullptr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -126,7 +148,36 @@ hipError_t launch_mode(const Shape &sh, const FwdArgs &a, hipStream_t stream)
     return uniform_hi ? launch_mode<MODE, true>(sh, a, stream) : launch_mode<MODE, false>(sh, a, stream);
 }
 
+// Clock probe: the kernel of the default vector-store shape (unroll 2 for
+// FP64, 4 otherwise) with stamps; stamps holds 4 entries per workgroup.
+template <int MODE>
+hipError_t launch_clock_mode(const Shape &sh, const FwdArgs &a, uint64_t *stamps, hipStream_t stream)
+{
+    constexpr int U = MODE == kModeF64 ? 2 : 4;
+    if (sh.unroll != U) return hipErrorInvalidValue;
+    dim3 grid(sh.grid), block(sh.block);
+    const bool uniform_hi = a.n == 0 || (a.counter_offset >> 32) == ((a.counter_offset + a.n - 1) >> 32);
+    if (uniform_hi)
+        hipLaunchKernelGGL((forward_kernel<MODE, U, true, true>), grid, block, 0, stream, a, stamps);
+    else
+        hipLaunchKernelGGL((forward_kernel<MODE, U, false, true>), grid, block, 0, stream, a, stamps);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int forward_default_unroll(int mode) { return mode == kModeF64 ? 2 : 4; }
+
+hipError_t launch_forward_clock(int mode, const Shape &shape, const FwdArgs &args, uint64_t *stamps,
+                                hipStream_t stream)
+{
+    switch (mode) {
+    case kModeF64: return launch_clock_mode<kModeF64>(shape, args, stamps, stream);
+    case kModeF32: return launch_clock_mode<kModeF32>(shape, args, stamps, stream);
+    case kModeF32NoTail: return launch_clock_mode<kModeF32NoTail>(shape, args, stamps, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 // One thread per group of particles (the grid-stride loop runs once) up to
 // 2^30 blocks: consecutive workgroups then write consecutive address ranges,
@@ -139,7 +190,7 @@ Shape forward_shape(int mode, uint64_t n, bool vec)
 {
     Shape s;
     s.block = 256;
-    s.unroll = vec ? (mode == kModeF64 ? 2 : 4) : 1;
+    s.unroll = vec ? forward_default_unroll(mode) : 1;
     uint64_t per_cu = 0;
     if (const char *env = std::getenv("KAPPA_FORWARD_SHAPE")) {
         int b = 0, u = 0, w = -1;

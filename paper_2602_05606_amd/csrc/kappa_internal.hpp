@@ -49,6 +49,12 @@ struct FwdArgs {
 // Default shape for n particles in a mode; `vec` selects the vector-store path.
 Shape forward_shape(int mode, uint64_t n, bool vec);
 hipError_t launch_forward(int mode, const Shape &shape, bool vec, const FwdArgs &args, hipStream_t stream);
+// Unroll (particles per thread) of the default vector-store shape of a mode.
+int forward_default_unroll(int mode);
+// The forward kernel with per-workgroup clock stamps (4 uint64 per workgroup
+// of shape.grid); shape must be the default vector-store shape of the mode.
+hipError_t launch_forward_clock(int mode, const Shape &shape, const FwdArgs &args, uint64_t *stamps,
+                                hipStream_t stream);
 hipError_t launch_philox(uint64_t n, uint64_t counter_offset, uint32_t seg, uint32_t draw, uint32_t k0, uint32_t k1,
                          uint32_t *out, hipStream_t stream);
 hipError_t launch_fill_probe(int mode, uint64_t n, void *vx, void *vy, void *vz, hipStream_t stream);

@@ -145,6 +145,33 @@ def test_exact_and_probe_argument_checks():
     assert lib.kappa_philox(0, 0, 0, 0, 0, None, None) == _lib.OK
 
 
+def test_clock_probe_argument_checks():
+    lib = _lib.load()
+    blocks, hz = ctypes.c_uint32(7), ctypes.c_double(1.0)
+    args = (3.0, 1.0, 1 << 20, 0, 0, 0, 1, FAKE, FAKE, FAKE)
+    assert lib.kappa_clock_probe(*args, FAKE, 1 << 20, None, ctypes.byref(hz), None) == _lib.EINVAL
+    # n = 0: nothing launched, no workgroups
+    assert lib.kappa_clock_probe(3.0, 1.0, 0, 0, 0, 0, 1, None, None, None, None, 0,
+                                 ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.OK
+    assert blocks.value == 0
+    # outputs must allow the vector stores of the timed kernel
+    odd = ctypes.c_void_p(0x10004)
+    assert lib.kappa_clock_probe(3.0, 1.0, 1 << 20, 0, 0, 0, 1, FAKE, odd, FAKE, FAKE, 1 << 20,
+                                 ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.EALIGN
+    assert lib.kappa_clock_probe(*args, None, 1 << 20, ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.EINVAL
+    assert lib.kappa_clock_probe(*args, ctypes.c_void_p(0x10004), 1 << 20, ctypes.byref(blocks),
+                                 ctypes.byref(hz), None) == _lib.EALIGN
+    # too few stamps: the workgroup count is still reported (FP32: 4 particles
+    # per thread, 256 threads per workgroup), with no HIP call
+    assert lib.kappa_clock_probe(*args, FAKE, 4, ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.ERANGE
+    assert blocks.value == (1 << 20) // 1024
+    fp64 = (3.0, 1.0, 1 << 20, 0, 0, 0, 0, FAKE, FAKE, FAKE)
+    assert lib.kappa_clock_probe(*fp64, FAKE, 4, ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.ERANGE
+    assert blocks.value == (1 << 20) // 512
+    assert lib.kappa_clock_probe(1.5, *args[1:], FAKE, 1 << 20, ctypes.byref(blocks), ctypes.byref(hz),
+                                 None) == _lib.EINVAL
+
+
 def test_histogram_and_divergence_argument_checks():
     lib = _lib.load()
     assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, 1.0, 0.2, 0, FAKE, None) == _lib.ERANGE
