@@ -460,12 +460,13 @@ def main():
     if "rates" in chosen:
         per_kappa = {}
         for k in kappas:
-            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
+            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP32, out=out32), 20, torch, warm=10)
             per_kappa[str(k)] = n / (ms * 1e-3)
         extras["fp32_per_kappa_particles_per_s"] = per_kappa
-        ms = time_launches(lambda: kp.sample(math.inf, theta, n, seed, precision=kp.FP32, out=out32), 5, torch)
+        ms = time_launches(lambda: kp.sample(math.inf, theta, n, seed, precision=kp.FP32, out=out32), 20, torch,
+                           warm=10)
         extras["maxwell_limit_fp32_particles_per_s"] = n / (ms * 1e-3)
-        fill_ms = time_launches(lambda: kp.fill_probe(n, kp.FP32, out32), 5, torch)
+        fill_ms = time_launches(lambda: kp.fill_probe(n, kp.FP32, out32), 20, torch, warm=10)
         extras["store_probe_fp32"] = {"GB_per_s": 12 * n / (fill_ms * 1e-3) / 1e9,
                                       "particles_per_s": n / (fill_ms * 1e-3)}
         result["roofline"]["frac_of_store_probe"] = achieved / extras["store_probe_fp32"]["GB_per_s"]
@@ -513,7 +514,7 @@ def main():
         out64 = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
         fp64 = {}
         for k in kappas:
-            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP64, out=out64), 3, torch)
+            ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP64, out=out64), 10, torch, warm=5)
             fp64[str(k)] = {"particles_per_s": n / (ms * 1e-3), "GB_per_s": 24 * n / (ms * 1e-3) / 1e9}
         extras["fp64_per_kappa"] = fp64
         fill64 = time_launches(lambda: kp.fill_probe(n, kp.FP64, out64), 3, torch)

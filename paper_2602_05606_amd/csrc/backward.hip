@@ -82,18 +82,21 @@ __device__ __forceinline__ float dL_dkappa_f32(const InvF32 &inv)
     return z < 0.5f ? z * z * p : fmaf(z, inv.ez, -inv.em1);
 }
 
-// The generator's Philox block of particle counter_offset + j (as in the
+// The generator's Philox block of particle counter_offset + j0 + k, as in the
 // forward kernel: with HI_UNIFORM the launch's counters share their high word,
 // taken from the kernel argument so that the first rounds run partly on the
-// scalar unit; the words are the same).
+// scalar unit, and the first product M_A (base + k) is one multiply-add; the
+// words are the same.
 template <bool HI_UNIFORM>
-__device__ __forceinline__ Block4 bwd_block(const BwdArgs &a, uint64_t j)
+__device__ __forceinline__ Block4 bwd_block(const BwdArgs &a, uint64_t j0, int k)
 {
-    if constexpr (HI_UNIFORM)
-        return philox4x32_10(static_cast<uint32_t>(a.counter_offset) + static_cast<uint32_t>(j),
-                             static_cast<uint32_t>(a.counter_offset >> 32), a.seg, 0, a.k0, a.k1);
-    else
-        return particle_block(a.counter_offset + j, a.seg, 0, a.k0, a.k1);
+    if constexpr (HI_UNIFORM) {
+        const uint32_t base = static_cast<uint32_t>(a.counter_offset) + static_cast<uint32_t>(j0);
+        const uint64_t pa1 = static_cast<uint64_t>(kMulA) * base + static_cast<uint64_t>(kMulA) * static_cast<uint32_t>(k);
+        return philox4x32_10_lane(pa1, static_cast<uint32_t>(a.counter_offset >> 32), a.seg, 0, a.k0, a.k1);
+    } else {
+        return particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+    }
 }
 
 template <int MODE, int U, bool VEC, bool HI_UNIFORM>
@@ -128,7 +131,7 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             tail_dot[k] = 0.0f;
-            const Block4 b = bwd_block<HI_UNIFORM>(a, j0 + k);
+            const Block4 b = bwd_block<HI_UNIFORM>(a, j0, k);
             if constexpr (MODE == kModeF64) {
                 bool high;
                 double u;

@@ -39,7 +39,7 @@ namespace {
 constexpr uint64_t kTile = 1024;  // particles per tile of the segment map
 
 struct alignas(16) SegF32 {
-    float kstar, inv_kstar, ln2_inv_kstar, a, c, two_b, four_b, theta, dx, dy, dz;
+    float inv_kstar, a, neg_c_kstar, four_b_kstar, two_kstar, two_b, theta, dx, dy, dz;
     uint32_t seg_id;
 };
 
@@ -211,13 +211,12 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                 particle_f64(b, sp, x[k], y[k], z[k]);
             } else {
                 SpeciesF32 sp{};
-                sp.kstar = q.kstar;
                 sp.inv_kstar = q.inv_kstar;
-                sp.ln2_inv_kstar = q.ln2_inv_kstar;
                 sp.a = q.a;
-                sp.c = q.c;
+                sp.neg_c_kstar = q.neg_c_kstar;
+                sp.four_b_kstar = q.four_b_kstar;
+                sp.two_kstar = q.two_kstar;
                 sp.two_b = q.two_b;
-                sp.four_b = q.four_b;
                 sp.theta = q.theta;
                 particle_f32(b, sp, x[k], y[k], z[k]);
                 if constexpr (MODE == kModeF32) tails |= static_cast<uint32_t>(in_fp64_tail(b.r0)) << k;
@@ -485,7 +484,7 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
         const SpeciesF32 b = species_f32(it->second, segs[s].theta);
         s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.half_inv_b, a.theta,
                         segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
-        s32[s] = SegF32{b.kstar, b.inv_kstar, b.ln2_inv_kstar, b.a, b.c, b.two_b, b.four_b, b.theta,
+        s32[s] = SegF32{b.inv_kstar, b.a, b.neg_c_kstar, b.four_b_kstar, b.two_kstar, b.two_b, b.theta,
                         static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),
                         static_cast<float>(segs[s].drift[2]), segs[s].seg_id};
         ids[s] = segs[s].seg_id;

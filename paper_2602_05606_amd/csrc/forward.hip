@@ -37,19 +37,22 @@ __device__ __forceinline__ void store_group(T *p, const T (&v)[U])
     }
 }
 
-// Philox block of particle counter_offset + j.  When the launch's counter
+// Philox block of particle counter_offset + j0 + k.  When the launch's counter
 // range stays inside one block of 2^32 (HI_UNIFORM, nearly every launch), the
 // counter's high word is the same for all its particles and comes from the
-// kernel argument: Philox's first multiplies by words that are then uniform
-// run on the scalar unit (1.2% faster on gfx950).  The words are the same.
+// kernel argument, the first rounds run partly on the scalar unit, and the low
+// word base + k of the group's particles never carries, so its first product
+// M_A (base + k) = M_A base + M_A k is one multiply-add.  The words are the same.
 template <bool HI_UNIFORM>
-__device__ __forceinline__ Block4 fwd_block(const FwdArgs &a, uint64_t j)
+__device__ __forceinline__ Block4 fwd_block(const FwdArgs &a, uint64_t j0, int k)
 {
-    if constexpr (HI_UNIFORM)
-        return philox4x32_10(static_cast<uint32_t>(a.counter_offset) + static_cast<uint32_t>(j),
-                             static_cast<uint32_t>(a.counter_offset >> 32), a.seg, 0, a.k0, a.k1);
-    else
-        return particle_block(a.counter_offset + j, a.seg, 0, a.k0, a.k1);
+    if constexpr (HI_UNIFORM) {
+        const uint32_t base = static_cast<uint32_t>(a.counter_offset) + static_cast<uint32_t>(j0);
+        const uint64_t pa1 = static_cast<uint64_t>(kMulA) * base + static_cast<uint64_t>(kMulA) * static_cast<uint32_t>(k);
+        return philox4x32_10_lane(pa1, static_cast<uint32_t>(a.counter_offset >> 32), a.seg, 0, a.k0, a.k1);
+    } else {
+        return particle_block(a.counter_offset + j0 + k, a.seg, 0, a.k0, a.k1);
+    }
 }
 
 // CLOCK = true is the clock probe's instantiation: the same kernel, plus
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(256) forward_kernel(FwdArgs a, uint64_t *stamp
         uint32_t tails = 0;
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const Block4 b = fwd_block<HI_UNIFORM>(a, j0 + k);
+            const Block4 b = fwd_block<HI_UNIFORM>(a, j0, k);
             if constexpr (MODE == kModeF64) {
                 particle_f64(b, a.s64, x[k], y[k], z[k]);
             } else {

@@ -27,13 +27,71 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+
 __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
 {
-    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
-    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = static_cast<uint32_t>(pa);
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// Philox4x32-10 of a counter (c0, u1, u2, u3) whose words u1, u2, u3 are the
+// same in every lane of a launch (the high word of the particle index, seg and
+// draw): the words of philox4x32_10, with the first three rounds grouped so
+// that every product or XOR of uniform words runs on the scalar unit.  The
+// first product M_A c0 comes in as pa1, so that a caller can fold c0 = base + k
+// into one multiply-add.
+__device__ __forceinline__ Block4 philox4x32_10_lane(uint64_t pa1, uint32_t u1, uint32_t u2, uint32_t u3,
+                                                     uint32_t k0, uint32_t k1)
+{
+    // round 1: M_B u2 and the new c0 are uniform
+    const uint64_t pb1 = static_cast<uint64_t>(kMulB) * u2;
+    uint32_t c0 = static_cast<uint32_t>(pb1 >> 32) ^ u1 ^ k0;
+    uint32_t c1 = static_cast<uint32_t>(pb1);
+    uint32_t c2 = static_cast<uint32_t>(pa1 >> 32) ^ (u3 ^ k1);
+    uint32_t c3 = static_cast<uint32_t>(pa1);
+    k0 += kWeylA;
+    k1 += kWeylB;
+    {  // round 2: c0 and c1 uniform, so M_A c0 is too
+        const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ (c1 ^ k0);
+        const uint32_t n2 = c3 ^ (static_cast<uint32_t>(pa >> 32) ^ k1);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = static_cast<uint32_t>(pa);
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    {  // round 3: c3 uniform
+        const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ (c3 ^ k1);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = static_cast<uint32_t>(pa);
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
         const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
         const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
         const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
@@ -212,22 +270,37 @@ __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF
 }
 
 // FP32 path.  It runs on the hardware base-2 transcendentals (v_log_f32,
-// v_exp_f32), v_sqrt_f32 and v_rcp_f32, each within 2 ulp, and expm1 of
-// arguments in [-1/2, 1/2] by a degree-6 polynomial for expm1(x)/x
-// (near-minimax, Chebyshev nodes; 4e-9 approximation error, 8e-8 in FP32
-// evaluation).  Same evaluation order as invert_f64, in base 2.
-__device__ __forceinline__ float expm1_poly(float x)
+// v_exp_f32), v_sqrt_f32 and v_rsq_f32, each within 2 ulp, in base 2
+// throughout: with t = p / ln 2, e^p - 1 = 2^t - 1 is taken by a degree-4
+// polynomial for (2^t - 1) / t where |t| is small (two near-minimax fits at
+// Chebyshev nodes, one per argument range; approximation error <= 1.0e-7,
+// <= 1.8e-7 with FP32 evaluation).  Same evaluation order as invert_f64.
+
+// 2^t - 1 for t in [-2/3, 0] (the high side's U1^{2/3} - 1).
+__device__ __forceinline__ float exp2m1_neg(float t)
 {
-    float p = fmaf(0x1.a2a31ep-13f, x, 0x1.6ef178p-10f);
-    p = fmaf(p, x, 0x1.110fccp-7f);
-    p = fmaf(p, x, 0x1.55527ap-5f);
-    p = fmaf(p, x, 0x1.555556p-3f);
-    p = fmaf(p, x, 0x1.000002p-1f);
-    p = fmaf(p, x, 1.0f);
-    return x * p;
+    float p = fmaf(0x1.20ec64p-10f, t, 0x1.36e5bep-7f);
+    p = fmaf(p, t, 0x1.c6708p-5f);
+    p = fmaf(p, t, 0x1.ebfa8cp-3f);
+    p = fmaf(p, t, 0x1.62e42ep-1f);
+    return t * p;
 }
 
+// 2^t - 1 for t in [0, 1 / (2 ln 2)] (expm1(z) for z < 1/2).
+__device__ __forceinline__ float exp2m1_pos(float t)
+{
+    float p = fmaf(0x1.af907ep-10f, t, 0x1.34741cp-7f);
+    p = fmaf(p, t, 0x1.c7211p-5f);
+    p = fmaf(p, t, 0x1.ebf952p-3f);
+    p = fmaf(p, t, 0x1.62e432p-1f);
+    return t * p;
+}
+
+// Threshold of the small-argument branch: z = t ln 2 < 1/2.
+constexpr float kExp2m1Small = 0x1.715476p-1f;  // 1 / (2 ln 2)
+
 struct InvF32 {
+    float w;         // -log2(1 - U1^{2/3}) / kappa* = z / ln 2
     float z;         // -lT / kappa*
     float ez;        // e^z
     float em1;       // e^z - 1
@@ -238,6 +311,9 @@ struct InvF32 {
     __device__ __forceinline__ float sqrt_x() const { return num * __builtin_amdgcn_rsqf(num * den); }
 };
 
+// The species constants enter premultiplied (SpeciesF32): with L = -kappa* em1,
+// A = a + cL = a - (c kappa*) em1, A^2 - 4bL = A^2 + (4b kappa*) em1 and
+// -2L = (2 kappa*) em1, so L itself is formed only for the backward pass.
 __device__ __forceinline__ InvF32 invert_f32(bool high, float y1, float d1, const SpeciesF32 &s)
 {
     constexpr float kLog2e = 0x1.715476p+0f, kLn2 = 0x1.62e430p-1f;
@@ -247,19 +323,20 @@ __device__ __forceinline__ InvF32 invert_f32(bool high, float y1, float d1, cons
     const float l1 = fmaf(d1, kLog2e, __builtin_amdgcn_logf(y1));
     const float p2 = l1 * (2.0f / 3.0f);               // log2 U1^{2/3}
     const float e = __builtin_amdgcn_exp2f(p2);         // U1^{2/3} (low side)
-    const float em1q = expm1_poly(p2 * kLn2);           // U1^{2/3} - 1 (high side, |arg| <= 0.47)
+    const float em1q = exp2m1_neg(p2);                  // U1^{2/3} - 1 (high side, p2 in [-2/3, 0])
     const float y2 = high ? -em1q : 1.0f - e;
     const float d2 = high ? 0.0f : (1.0f - y2) - e;
     const float lT2 = fmaf(d2, kLog2e, __builtin_amdgcn_logf(y2));  // log2(1 - U1^{2/3})
     InvF32 r;
-    r.z = -lT2 * s.ln2_inv_kstar;
-    r.ez = __builtin_amdgcn_exp2f(-lT2 * s.inv_kstar);
-    r.em1 = (r.z < 0.5f) ? expm1_poly(r.z) : r.ez - 1.0f;
+    r.w = -lT2 * s.inv_kstar;
+    r.z = r.w * kLn2;
+    r.ez = __builtin_amdgcn_exp2f(r.w);
+    r.em1 = (r.w < kExp2m1Small) ? exp2m1_pos(r.w) : r.ez - 1.0f;
     r.L = -s.kstar * r.em1;
-    const float A = fmaf(s.c, r.L, s.a);
-    r.D = __builtin_amdgcn_sqrtf(fmaf(A, A, -s.four_b * r.L));
+    const float A = fmaf(r.em1, s.neg_c_kstar, s.a);
+    r.D = __builtin_amdgcn_sqrtf(fmaf(r.em1, s.four_b_kstar, A * A));
     const bool pos = A >= 0.0f;
-    r.num = pos ? -2.0f * r.L : r.D - A;
+    r.num = pos ? r.em1 * s.two_kstar : r.D - A;
     r.den = pos ? A + r.D : s.two_b;
     return r;
 }
@@ -324,7 +401,8 @@ __device__ __forceinline__ DirF64 direction_f64(uint32_t r1, uint32_t r2)
 }
 
 struct DirF32 {
-    float cx, cy, cz;
+    float cx, cy, cz;  // unit vector
+    float st, cphi, sphi;  // sin(theta), cos(phi), sin(phi): cy = st cphi, cz = st sphi
 };
 
 // v_sin_f32 / v_cos_f32 take their argument in revolutions, so sin(2 pi U3)
@@ -341,8 +419,11 @@ __device__ __forceinline__ DirF32 direction_f32(uint32_t r1, uint32_t r2)
     const float u3 = fmaf(static_cast<float>(r2), 0x1p-32f, 0x1p-33f);
     DirF32 d;
     d.cx = 0.5f * (opc - omc);
-    d.cy = st * __builtin_amdgcn_cosf(u3);
-    d.cz = st * __builtin_amdgcn_sinf(u3);
+    d.st = st;
+    d.cphi = __builtin_amdgcn_cosf(u3);
+    d.sphi = __builtin_amdgcn_sinf(u3);
+    d.cy = st * d.cphi;
+    d.cz = st * d.sphi;
     return d;
 }
 
@@ -373,9 +454,10 @@ __device__ __forceinline__ void particle_f32(const Block4 &b, const SpeciesF32 &
     const InvF32 inv = invert_f32(high, y1, d1, s);
     const float V = s.theta * inv.sqrt_x();
     const DirF32 d = direction_f32(b.r1, b.r2);
+    const float Vs = V * d.st;  // V sin(theta), shared by vy and vz
     vx = V * d.cx;
-    vy = V * d.cy;
-    vz = V * d.cz;
+    vy = Vs * d.cphi;
+    vz = Vs * d.sphi;
 }
 
 // FP32-mode particle whose 1 - U1 is below 2^-20: the speed is inverted in

@@ -27,7 +27,7 @@ struct SpeciesF64 {
 
 struct SpeciesF32 {
     float kstar, inv_kstar, a, b, c, half_inv_b, theta;
-    float ln2_inv_kstar, two_b, four_b;  // ln 2 / kappa*, 2b, 4b
+    float two_b, two_kstar, neg_c_kstar, four_b_kstar;  // 2b, 2 kappa*, -c kappa*, 4b kappa*
     float da, db, dc;
 };
 

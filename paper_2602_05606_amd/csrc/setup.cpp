@@ -97,9 +97,10 @@ SpeciesF32 species_f32(const Setup &s, double theta)
     p.c = static_cast<float>(s.c);
     p.half_inv_b = static_cast<float>(0.5 / s.b);
     p.theta = static_cast<float>(theta);
-    p.ln2_inv_kstar = static_cast<float>(0.6931471805599453 / ks);
     p.two_b = static_cast<float>(2.0 * s.b);
-    p.four_b = static_cast<float>(4.0 * s.b);
+    p.two_kstar = static_cast<float>(2.0 * ks);
+    p.neg_c_kstar = static_cast<float>(-s.c * ks);
+    p.four_b_kstar = static_cast<float>(4.0 * s.b * ks);
     p.da = static_cast<float>(s.da);
     p.db = static_cast<float>(s.db);
     p.dc = static_cast<float>(s.dc);
