@@ -44,7 +44,7 @@ struct alignas(16) SegF32 {
 };
 
 struct alignas(16) SegF64 {
-    double kstar, inv_kstar, a, b, c, half_inv_b, theta, dx, dy, dz;
+    double kstar, inv_kstar, a, b, c, two_b, neg_four_b, theta, dx, dy, dz;
 };
 
 struct CellF32 {
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
             const Block4 b = particle_block(j - seg_begin, seg_id, 0, a.k0, a.k1);
             const auto &q = prm.q;
             if constexpr (MODE == kModeF64) {
-                SpeciesF64 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.half_inv_b, q.theta, 0, 0, 0};
+                SpeciesF64 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.two_b, q.neg_four_b, q.theta, 0, 0, 0};
                 particle_f64(b, sp, x[k], y[k], z[k]);
             } else {
                 SpeciesF32 sp{};
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                         const uint32_t sq = seg_of[k];
                         const SegF64 w = a.seg64[sq];
                         const SegF32 f = a.seg32[sq];
-                        const SpeciesF64 s64{w.kstar, w.inv_kstar, w.a, w.b, w.c, w.half_inv_b, w.theta, 0, 0, 0};
+                        const SpeciesF64 s64{w.kstar, w.inv_kstar, w.a, w.b, w.c, w.two_b, w.neg_four_b, w.theta, 0, 0, 0};
                         const Block4 b = particle_block(j0 + k - a.start[sq], a.seg_ids[sq], 0, a.k0, a.k1);
                         tail_particle_f32(b, s64, x[k], y[k], z[k]);
                         x[k] += f.dx;
@@ -482,7 +482,7 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
         if (it == setups.end()) it = setups.emplace(segs[s].kappa, make_setup(segs[s].kappa)).first;
         const SpeciesF64 a = species_f64(it->second, segs[s].theta);
         const SpeciesF32 b = species_f32(it->second, segs[s].theta);
-        s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.half_inv_b, a.theta,
+        s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.two_b, a.neg_four_b, a.theta,
                         segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
         s32[s] = SegF32{b.inv_kstar, b.a, b.neg_c_kstar, b.four_b_kstar, b.two_kstar, b.two_b, b.theta,
                         static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),

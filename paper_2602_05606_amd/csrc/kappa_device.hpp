@@ -262,10 +262,10 @@ __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF
     exp_expm1_f64(r.z, r.ez, r.em1);
     r.L = -s.kstar * r.em1;
     const double A = fma(s.c, r.L, s.a);
-    r.D = sqrt(fma(A, A, -4.0 * s.b * r.L));
+    r.D = sqrt(fma(A, A, s.neg_four_b * r.L));
     const bool pos = A >= 0.0;
     r.num = pos ? -2.0 * r.L : r.D - A;
-    r.den = pos ? A + r.D : 2.0 * s.b;
+    r.den = pos ? A + r.D : s.two_b;
     return r;
 }
 

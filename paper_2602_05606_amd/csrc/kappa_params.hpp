@@ -19,9 +19,11 @@ Setup make_setup(double kappa);
 // kappa-derivative of ln B(3/2, kappa*).
 double digamma(double x);
 
-// Kernel-side copies, FP64 and FP32.  half_inv_b = 1 / (2b).
+// Kernel-side copies, FP64 and FP32.
 struct SpeciesF64 {
-    double kstar, inv_kstar, a, b, c, half_inv_b, theta;
+    double kstar, inv_kstar, a, b, c;
+    double two_b, neg_four_b;  // 2b, -4b
+    double theta;
     double da, db, dc;  // kappa-derivatives (backward only)
 };
 

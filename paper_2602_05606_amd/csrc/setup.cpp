@@ -78,7 +78,8 @@ SpeciesF64 species_f64(const Setup &s, double theta)
     p.a = s.a;
     p.b = s.b;
     p.c = s.c;
-    p.half_inv_b = 0.5 / s.b;
+    p.two_b = 2.0 * s.b;
+    p.neg_four_b = -4.0 * s.b;
     p.theta = theta;
     p.da = s.da;
     p.db = s.db;
