@@ -66,20 +66,18 @@ __device__ __forceinline__ double dk_term_f64(const InvF64 &inv, const SpeciesF6
     return vg * (-num / inv.D) / (2.0 * x);
 }
 
-// dL/dkappa at fixed U1 in FP32: z e^z - expm1(z).  For z < 1/2 the two terms
-// cancel to z^2/2, so the series z^2 sum_{n>=2} (n-1)/n! z^(n-2) is used
-// (truncated after n = 9, relative error < 2e-8 at z = 1/2).
+// dL/dkappa at fixed U1 in FP32: z e^z - expm1(z), z = w ln 2.  For z < 1/2
+// the two terms cancel to z^2/2, so there it is taken as w^2 Q(w) with Q a
+// degree-4 near-minimax fit of (z e^z - expm1(z)) / w^2 on [0, 1/(2 ln 2)]
+// (Chebyshev nodes; 2.6e-7 relative with FP32 evaluation).
 __device__ __forceinline__ float dL_dkappa_f32(const InvF32 &inv)
 {
-    const float z = inv.z;
-    float p = fmaf(1.0f / 45360.0f, z, 1.0f / 5760.0f);
-    p = fmaf(p, z, 1.0f / 840.0f);
-    p = fmaf(p, z, 1.0f / 144.0f);
-    p = fmaf(p, z, 1.0f / 30.0f);
-    p = fmaf(p, z, 1.0f / 8.0f);
-    p = fmaf(p, z, 1.0f / 3.0f);
-    p = fmaf(p, z, 0.5f);
-    return z < 0.5f ? z * z * p : fmaf(z, inv.ez, -inv.em1);
+    const float w = inv.w;
+    float q = fmaf(0x1.f58396p-11f, w, 0x1.558744p-8f);
+    q = fmaf(q, w, 0x1.d9463cp-6f);
+    q = fmaf(q, w, 0x1.c6ad82p-4f);
+    q = fmaf(q, w, 0x1.ebfbe6p-3f);
+    return w < kExp2m1Small ? (w * w) * q : fmaf(inv.z, inv.ez, -inv.em1);
 }
 
 // The generator's Philox block of particle counter_offset + j0 + k, as in the
@@ -148,20 +146,21 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                 speed_uniform_f32(b.r0, b.r3, high, y1, d1);
                 const InvF32 inv = invert_f32(high, y1, d1, a.s32);
                 const DirF32 d = direction_f32(b.r1, b.r2);
-                const float dot = d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k];
-                if (MODE == kModeF32 && __builtin_expect(in_fp64_tail(b.r0), 0)) {
-                    tail_dot[k] = dot;
-                    tails |= 1u << k;
-                } else {
-                    const float x = inv.x();
-                    const float V = a.s32.theta * __builtin_amdgcn_sqrtf(x);
-                    const float vg = V * dot;
-                    const float dL = dL_dkappa_f32(inv);
-                    const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
-                    const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
-                    grp_s += vg;
-                    grp_k += term;
-                }
+                // g . direction with cy = sin(theta) cos(phi), cz = sin(theta) sin(phi)
+                const float dot = fmaf(d.st, fmaf(d.cphi, uy[k], d.sphi * uz[k]), d.cx * ux[k]);
+                // Every lane takes the FP32 terms (straight-line code over the U particles);
+                // the rare tail lanes drop them and are redone in FP64 below.
+                const bool tail = MODE == kModeF32 && in_fp64_tail(b.r0);
+                tail_dot[k] = dot;
+                tails |= static_cast<uint32_t>(tail) << k;
+                const float sx = inv.sqrt_x();  // V / theta
+                const float x = sx * sx;
+                const float vg = a.s32.theta * sx * dot;
+                const float dL = dL_dkappa_f32(inv);
+                const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
+                const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
+                grp_s += tail ? 0.0f : vg;
+                grp_k += tail ? 0.0f : term;
             }
         }
         if constexpr (MODE != kModeF64) {
