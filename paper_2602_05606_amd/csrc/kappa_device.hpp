@@ -131,9 +131,11 @@ __device__ __forceinline__ Block4 particle_block(uint64_t i, uint32_t seg, uint3
 
 // e^p and e^p - 1 from one argument reduction (the textbook method: Cody and
 // Waite's two-part ln 2, then a polynomial on |r| <= ln2/2): p = k ln2 + r,
-// q = expm1(r) by its Taylor series to r^13 (truncation < 2e-17 relative),
+// q = expm1(r) = r + r^2 t(r) with t a degree-10 near-minimax fit (Chebyshev
+// nodes, 60-digit arithmetic; 1.1e-16 relative for q with FP64 evaluation),
 // e^p = 2^k (1 + q), e^p - 1 = 2^k q + (2^k - 1).  The last form has no
-// harmful cancellation for any k (|q| <= 0.42).
+// harmful cancellation for any k (|q| <= 0.42).  2^k is assembled from its
+// exponent bits: the callers' |p| stay far inside the normal range.
 __device__ __forceinline__ void exp_expm1_f64(double p, double &e, double &em1)
 {
     constexpr double kLog2e = 0x1.71547652b82fep+0;
@@ -141,30 +143,29 @@ __device__ __forceinline__ void exp_expm1_f64(double p, double &e, double &em1)
     const double k = rint(p * kLog2e);
     double r = fma(-k, kLn2Hi, p);
     r = fma(-k, kLn2Lo, r);
-    double t = 1.0 / 6227020800.0;            // 1/13!
-    t = fma(t, r, 1.0 / 479001600.0);         // 1/12!
-    t = fma(t, r, 1.0 / 39916800.0);
-    t = fma(t, r, 1.0 / 3628800.0);
-    t = fma(t, r, 1.0 / 362880.0);
-    t = fma(t, r, 1.0 / 40320.0);
-    t = fma(t, r, 1.0 / 5040.0);
-    t = fma(t, r, 1.0 / 720.0);
-    t = fma(t, r, 1.0 / 120.0);
-    t = fma(t, r, 1.0 / 24.0);
-    t = fma(t, r, 1.0 / 6.0);
+    double t = 0x1.1f72fc730b4ffp-29;
+    t = fma(t, r, 0x1.af4ddd84882fep-26);
+    t = fma(t, r, 0x1.27e4db67b4303p-22);
+    t = fma(t, r, 0x1.71de02375656cp-19);
+    t = fma(t, r, 0x1.a01a01a6d7808p-16);
+    t = fma(t, r, 0x1.a01a01abe62ddp-13);
+    t = fma(t, r, 0x1.6c16c16c162d6p-10);
+    t = fma(t, r, 0x1.11111111100dfp-7);
+    t = fma(t, r, 0x1.5555555555556p-5);
+    t = fma(t, r, 0x1.5555555555557p-3);
     t = fma(t, r, 0.5);
-    t = fma(t, r, 1.0);
-    const double q = r * t;                   // expm1(r)
-    const int ki = static_cast<int>(k);
-    e = ldexp(1.0 + q, ki);
-    em1 = fma(q, ldexp(1.0, ki), ldexp(1.0, ki) - 1.0);
+    const double q = fma(r * r, t, r);        // expm1(r)
+    const double pk = __hiloint2double((static_cast<int>(k) + 1023) << 20, 0);  // 2^k
+    e = fma(q, pk, pk);
+    em1 = fma(q, pk, pk - 1.0);
 }
 
 // Natural log of x in (0, 1] (normal doubles), within a few ulp: x = m 2^e
 // with m in [sqrt(1/2), sqrt(2)), f = m - 1 (exact), and
-// log(1 + f) = 2 atanh(s) = 2s + 2s^3/3 + 2s^5/5 + ..., s = f / (2 + f),
-// |s| <= 0.172; the series is summed to s^21 (truncation < 1e-17 relative).
-// The division is one v_rcp_f64 step refined by a Newton correction.
+// log(1 + f) = 2 atanh(s) = 2s + s z Q(z), s = f / (2 + f), z = s^2 <= 0.0295,
+// Q a degree-6 near-minimax fit of (2 atanh(s)/s - 2)/z (1.1e-16 relative for
+// the log with FP64 evaluation).  The division is one v_rcp_f64 step refined
+// by a Newton correction.
 __device__ __forceinline__ double log_unit_f64(double x)
 {
     constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
@@ -179,48 +180,43 @@ __device__ __forceinline__ double log_unit_f64(double x)
     double sv = f * rc;
     sv = fma(fma(-sv, den, f), rc, sv);          // one Newton correction of f / den
     const double z = sv * sv;
-    double q = 2.0 / 21.0;
-    q = fma(q, z, 2.0 / 19.0);
-    q = fma(q, z, 2.0 / 17.0);
-    q = fma(q, z, 2.0 / 15.0);
-    q = fma(q, z, 2.0 / 13.0);
-    q = fma(q, z, 2.0 / 11.0);
-    q = fma(q, z, 2.0 / 9.0);
-    q = fma(q, z, 2.0 / 7.0);
-    q = fma(q, z, 2.0 / 5.0);
-    q = fma(q, z, 2.0 / 3.0);
+    double q = 0x1.2b584aae78a57p-3;
+    q = fma(q, z, 0x1.39fe606542ddep-3);
+    q = fma(q, z, 0x1.7462b4ab2ef6bp-3);
+    q = fma(q, z, 0x1.c71c62e5800a1p-3);
+    q = fma(q, z, 0x1.2492492df148dp-2);
+    q = fma(q, z, 0x1.99999999952e2p-2);
+    q = fma(q, z, 0x1.5555555555558p-1);
     const double ed = static_cast<double>(e);
     const double lo = fma(ed, kLn2Lo, sv * z * q);
     return fma(ed, kLn2Hi, fma(2.0, sv, lo));
 }
 
 // sin(pi x) and cos(pi x) for x = (2 r + 1) 2^-32 in (0, 2), exact in double:
-// n = rint(2x), r = x - n/2 in [-1/4, 1/4] (exact), Taylor series of
-// sin(pi r) to (pi r)^17 and of cos(pi r) to (pi r)^18 (truncation below
-// 1e-19), then the quadrant n mod 4 swaps and signs the pair.
+// n = rint(2x), r = x - n/2 in [-1/4, 1/4] (exact), t = pi r, then
+// sin t = t - t^3 S(t^2) and cos t = 1 - t^2 C(t^2) with S and C degree-6
+// near-minimax fits on |t| <= pi/4 (1.1e-16 relative with FP64 evaluation);
+// the quadrant n mod 4 swaps and signs the pair.
 __device__ __forceinline__ void sincospi_f64(double x, double &sn, double &cs)
 {
     const double n = rint(2.0 * x);
     const double r = fma(-0.5, n, x);
     const double t = r * 0x1.921fb54442d18p+1;   // pi r, |t| <= pi/4
     const double t2 = t * t;
-    double ps = -1.0 / 355687428096000.0;        // -1/17!
-    ps = fma(ps, t2, 1.0 / 1307674368000.0);     // 1/15!
-    ps = fma(ps, t2, -1.0 / 6227020800.0);
-    ps = fma(ps, t2, 1.0 / 39916800.0);
-    ps = fma(ps, t2, -1.0 / 362880.0);
-    ps = fma(ps, t2, 1.0 / 5040.0);
-    ps = fma(ps, t2, -1.0 / 120.0);
-    ps = fma(ps, t2, 1.0 / 6.0);
+    double ps = 0x1.ab17d404de5b3p-41;
+    ps = fma(ps, t2, -0x1.61217f0b800d5p-33);
+    ps = fma(ps, t2, 0x1.ae645412c560cp-26);
+    ps = fma(ps, t2, -0x1.71de3a546095bp-19);
+    ps = fma(ps, t2, 0x1.a01a01a019938p-13);
+    ps = fma(ps, t2, -0x1.1111111111110p-7);
+    ps = fma(ps, t2, 0x1.5555555555555p-3);
     const double sr = fma(-t * t2, ps, t);       // sin(pi r)
-    double pc = 1.0 / 6402373705728000.0;        // 1/18!
-    pc = fma(pc, t2, -1.0 / 20922789888000.0);   // -1/16!
-    pc = fma(pc, t2, 1.0 / 87178291200.0);
-    pc = fma(pc, t2, -1.0 / 479001600.0);
-    pc = fma(pc, t2, 1.0 / 3628800.0);
-    pc = fma(pc, t2, -1.0 / 40320.0);
-    pc = fma(pc, t2, 1.0 / 720.0);
-    pc = fma(pc, t2, -1.0 / 24.0);
+    double pc = 0x1.8ff9d439a204ap-37;
+    pc = fma(pc, t2, -0x1.1eea7f259b344p-29);
+    pc = fma(pc, t2, 0x1.27e4f8e4a2e74p-22);
+    pc = fma(pc, t2, -0x1.a01a019de131fp-16);
+    pc = fma(pc, t2, 0x1.6c16c16c15d79p-10);
+    pc = fma(pc, t2, -0x1.5555555555551p-5);
     pc = fma(pc, t2, 0.5);
     const double cr = fma(-t2, pc, 1.0);         // cos(pi r)
     const int q = static_cast<int>(n) & 3;
@@ -228,6 +224,24 @@ __device__ __forceinline__ void sincospi_f64(double x, double &sn, double &cs)
     const double b = (q & 1) ? sr : cr;
     sn = (q & 2) ? -a : a;
     cs = ((q + 1) & 2) ? -b : b;
+}
+
+// 1/sqrt(a) and sqrt(a) for positive normal doubles (every caller's argument
+// is one): v_rsq_f64's estimate y with relative error e0, refined by one step
+// of the second-order iteration y (1 + e/2 + 3e^2/8), e = 1 - a y^2, which
+// leaves O(e0^3); sqrt(a) = a y, then one Newton correction (a - g^2)/(2g).
+__device__ __forceinline__ double rsqrt_pos_f64(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    const double e = fma(-a * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ double sqrt_pos_f64(double a)
+{
+    const double y = rsqrt_pos_f64(a);
+    const double g = a * y;
+    return fma(fma(-g, g, a), 0.5 * y, g);
 }
 
 struct InvF64 {
@@ -238,7 +252,7 @@ struct InvF64 {
     double D;    // sqrt(A^2 - 4bL)
     double num, den;  // x = (V/theta)^2 = num / den, both > 0
     __device__ __forceinline__ double x() const { return num / den; }
-    __device__ __forceinline__ double sqrt_x() const { return num * rsqrt(num * den); }
+    __device__ __forceinline__ double sqrt_x() const { return num * rsqrt_pos_f64(num * den); }
 };
 
 __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF64 &s)
@@ -262,7 +276,7 @@ __device__ __forceinline__ InvF64 invert_f64(bool high, double u, const SpeciesF
     exp_expm1_f64(r.z, r.ez, r.em1);
     r.L = -s.kstar * r.em1;
     const double A = fma(s.c, r.L, s.a);
-    r.D = sqrt(fma(A, A, s.neg_four_b * r.L));
+    r.D = sqrt_pos_f64(fma(A, A, s.neg_four_b * r.L));
     const bool pos = A >= 0.0;
     r.num = pos ? -2.0 * r.L : r.D - A;
     r.den = pos ? A + r.D : s.two_b;
@@ -389,7 +403,7 @@ struct DirF64 {
 __device__ __forceinline__ DirF64 direction_f64(uint32_t r1, uint32_t r2)
 {
     const double ct = static_cast<double>(static_cast<int64_t>(2 * static_cast<uint64_t>(r1) + 1) - (1ll << 32)) * 0x1p-32;
-    const double st = sqrt((1.0 - ct) * (1.0 + ct));  // both factors exact
+    const double st = sqrt_pos_f64((1.0 - ct) * (1.0 + ct));  // both factors exact
     const double u3x2 = static_cast<double>(2 * static_cast<uint64_t>(r2) + 1) * 0x1p-32;  // 2 U3
     double sp, cp;
     sincospi_f64(u3x2, sp, cp);
