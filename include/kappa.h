@@ -359,9 +359,10 @@ KAPPA_API kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t byt
  *   blocks      host; written with the number of workgroups of the launch
  *               (also when stamps_len is too small: then KAPPA_ERANGE).
  *               4 * ceil(n / 64) entries always suffice.
- * The outputs must be 16-byte aligned (KAPPA_EALIGN otherwise) and the
- * launch shape the default one (KAPPA_EINVAL when KAPPA_FORWARD_SHAPE
- * changes the particles per thread).  n = 0 writes *blocks = 0 and launches
+ * The outputs must be 16-byte aligned (KAPPA_EALIGN otherwise), the launch
+ * shape the default one (KAPPA_EINVAL when KAPPA_FORWARD_SHAPE changes the
+ * particles per thread), and n within one launch (2^40 particles in FP32,
+ * 2^39 in FP64; KAPPA_ERANGE otherwise).  n = 0 writes *blocks = 0 and launches
  * nothing.  Asynchronous like kappa_sample. */
 KAPPA_API kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed,
                                          uint64_t counter_offset, uint32_t seg_id, int precision, void *vx, void *vy,

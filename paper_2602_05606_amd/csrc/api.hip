@@ -207,6 +207,8 @@ kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t 
     const Shape shape = forward_shape(precision, n, true);
     if (shape.unroll != forward_default_unroll(precision))
         return fail(KAPPA_EINVAL, "the clock probe times the default shape (KAPPA_FORWARD_SHAPE overrides the unroll)");
+    if (static_cast<uint64_t>(shape.grid) * shape.block * shape.unroll < n)
+        return fail(KAPPA_ERANGE, "the clock probe times one launch: n exceeds what one launch covers");
     *blocks = static_cast<uint32_t>(shape.grid);
     if (stamps_len / 4 < static_cast<uint64_t>(shape.grid))
         return fail(KAPPA_ERANGE, "stamps holds %llu entries, the launch needs 4 x %d",

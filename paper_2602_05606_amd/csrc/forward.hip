@@ -76,9 +76,11 @@ __global__ void __launch_bounds__(256) forward_kernel(FwdArgs a, uint64_t *stamp
     T *vx = static_cast<T *>(a.vx);
     T *vy = static_cast<T *>(a.vy);
     T *vz = static_cast<T *>(a.vz);
+    // One group of U particles per thread and no loop: the launcher's grid
+    // covers every group, and with no loop the compiler keeps no constants
+    // live across one (on the FP64 path that spared every SGPR spill).
     const uint64_t ngroups = (a.n + U - 1) / U;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
+    if (const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups) {
         const uint64_t j0 = g * U;
         T x[U], y[U], z[U];
         uint32_t tails = 0;
@@ -182,31 +184,40 @@ hipError_t launch_forward_clock(int mode, const Shape &shape, const FwdArgs &arg
     }
 }
 
-// One thread per group of particles (the grid-stride loop runs once) up to
-// 2^30 blocks: consecutive workgroups then write consecutive address ranges,
-// which measured faster for streaming stores on gfx950 than a grid capped at
-// a few workgroups per CU striding over the arrays.
-// The environment variable KAPPA_FORWARD_SHAPE="block,unroll,blocks_per_cu"
-// overrides the shape for tuning (block in {64,128,256}, unroll in {1,2,4,8},
-// blocks_per_cu 0 for one thread per group).  Results never depend on it.
+// One thread per group of particles: consecutive workgroups write
+// consecutive address ranges, which measured faster for streaming stores on
+// gfx950 than a grid capped at a few workgroups per CU striding over the
+// arrays.  A launch holds at most max_grid workgroups (2^30; the environment
+// variable KAPPA_FORWARD_MAX_GRID lowers it, for tests): launch_forward splits
+// larger calls into consecutive chunks.  KAPPA_FORWARD_SHAPE="block,unroll"
+// overrides the shape for tuning (block in {64,128,256}, unroll in {1,2,4,8}).
+// Results never depend on either.
+uint64_t forward_max_grid()
+{
+    uint64_t cap = 1ull << 30;
+    if (const char *env = std::getenv("KAPPA_FORWARD_MAX_GRID")) {
+        const long long v = std::strtoll(env, nullptr, 10);
+        if (v > 0 && v < static_cast<long long>(cap)) cap = static_cast<uint64_t>(v);
+    }
+    return cap;
+}
+
 Shape forward_shape(int mode, uint64_t n, bool vec)
 {
     Shape s;
     s.block = 256;
     s.unroll = vec ? forward_default_unroll(mode) : 1;
-    uint64_t per_cu = 0;
     if (const char *env = std::getenv("KAPPA_FORWARD_SHAPE")) {
-        int b = 0, u = 0, w = -1;
-        if (std::sscanf(env, "%d,%d,%d", &b, &u, &w) == 3 && (b == 64 || b == 128 || b == 256) &&
-            (u == 1 || u == 2 || u == 4 || u == 8) && w >= 0) {
+        int b = 0, u = 0;
+        if (std::sscanf(env, "%d,%d", &b, &u) == 2 && (b == 64 || b == 128 || b == 256) &&
+            (u == 1 || u == 2 || u == 4 || u == 8)) {
             s.block = b;
             s.unroll = vec ? u : 1;
-            per_cu = static_cast<uint64_t>(w);
         }
     }
     const uint64_t groups = (n + s.unroll - 1) / s.unroll;
     const uint64_t need = (groups + s.block - 1) / s.block;
-    const uint64_t cap = per_cu ? per_cu * static_cast<uint64_t>(device_cu_count()) : (1ull << 30);
+    const uint64_t cap = forward_max_grid();
     s.grid = static_cast<int>(need < cap ? (need > 0 ? need : 1) : cap);
     return s;
 }
@@ -215,12 +226,31 @@ hipError_t launch_forward(int mode, const Shape &shape, bool vec, const FwdArgs 
 {
     Shape sh = shape;
     if (!vec) sh.unroll = 1;
-    switch (mode) {
-    case kModeF64: return launch_mode<kModeF64>(sh, args, stream);
-    case kModeF32: return launch_mode<kModeF32>(sh, args, stream);
-    case kModeF32NoTail: return launch_mode<kModeF32NoTail>(sh, args, stream);
-    default: return hipErrorInvalidValue;
+    // chunks of at most sh.grid workgroups; each starts on a multiple of
+    // block * unroll particles, so 16-byte alignment carries over
+    const uint64_t chunk = static_cast<uint64_t>(sh.grid) * sh.block * sh.unroll;
+    const size_t esz = mode == kModeF64 ? 8 : 4;
+    for (uint64_t first = 0; first < args.n || first == 0; first += chunk) {
+        FwdArgs a = args;
+        a.n = args.n - first < chunk ? args.n - first : chunk;
+        a.counter_offset = args.counter_offset + first;
+        a.vx = static_cast<char *>(args.vx) + first * esz;
+        a.vy = static_cast<char *>(args.vy) + first * esz;
+        a.vz = static_cast<char *>(args.vz) + first * esz;
+        Shape c = sh;
+        const uint64_t need = ((a.n + sh.unroll - 1) / sh.unroll + sh.block - 1) / sh.block;
+        c.grid = static_cast<int>(need > 0 ? need : 1);
+        hipError_t err;
+        switch (mode) {
+        case kModeF64: err = launch_mode<kModeF64>(c, a, stream); break;
+        case kModeF32: err = launch_mode<kModeF32>(c, a, stream); break;
+        case kModeF32NoTail: err = launch_mode<kModeF32NoTail>(c, a, stream); break;
+        default: return hipErrorInvalidValue;
+        }
+        if (err != hipSuccess) return err;
+        if (args.n - first <= chunk) break;
     }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

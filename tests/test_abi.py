@@ -172,6 +172,19 @@ def test_clock_probe_argument_checks():
                                  None) == _lib.EINVAL
 
 
+def test_clock_probe_needs_one_launch(monkeypatch):
+    # with at most 4 workgroups per launch, 2^20 particles need several launches,
+    # which the probe (one launch, one stamp per workgroup) refuses
+    monkeypatch.setenv("KAPPA_FORWARD_MAX_GRID", "4")
+    lib = _lib.load()
+    blocks, hz = ctypes.c_uint32(7), ctypes.c_double(1.0)
+    assert lib.kappa_clock_probe(3.0, 1.0, 1 << 20, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, 1 << 20,
+                                 ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.ERANGE
+    assert lib.kappa_clock_probe(3.0, 1.0, 4096, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, 3,
+                                 ctypes.byref(blocks), ctypes.byref(hz), None) == _lib.ERANGE
+    assert blocks.value == 4  # 4096 particles fit one launch of 4 workgroups; 3 stamps are too few
+
+
 def test_histogram_and_divergence_argument_checks():
     lib = _lib.load()
     assert lib.kappa_speed_histogram(FAKE, FAKE, FAKE, 10, 1, 1.0, 0.2, 0, FAKE, None) == _lib.ERANGE

@@ -192,3 +192,24 @@ def test_device_errors_are_reported():
     p = ctypes.c_void_p(buf.data_ptr() + 1)
     st = _lib.load().kappa_sample(3.0, 1.0, 4, 0, 0, 0, kp.FP32, p, p, p, None)
     assert st == _lib.EALIGN
+
+
+@pytest.mark.parametrize("prec", [kp.FP32, kp.FP64])
+def test_chunked_and_reshaped_launches_give_the_same_bits(prec, monkeypatch):
+    """A call larger than one launch runs as consecutive chunks; the launch
+    shape can be overridden for tuning.  Neither changes a bit of the output,
+    here over a counter range that crosses a 2^32 boundary (so chunks of both
+    kernel forms run)."""
+    n, off = 1_000_003, (1 << 32) - 5000
+    ref = [t.clone() for t in kp.sample(3.0, 1.0, n, 7, counter_offset=off, precision=prec)]
+    for env in ({"KAPPA_FORWARD_MAX_GRID": "3"}, {"KAPPA_FORWARD_MAX_GRID": "1000"},
+                {"KAPPA_FORWARD_SHAPE": "64,1"}, {"KAPPA_FORWARD_SHAPE": "128,8"},
+                {"KAPPA_FORWARD_SHAPE": "256,2", "KAPPA_FORWARD_MAX_GRID": "7"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        got = kp.sample(3.0, 1.0, n, 7, counter_offset=off, precision=prec)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), env
+        for k in env:
+            monkeypatch.delenv(k)
