@@ -28,10 +28,10 @@ KERNEL_SOURCES = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_0560
                   "paper_2602_05606_amd/csrc/kappa_params.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_fp32_c2.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_forward_fp32_c2.json")
-# VALU issue capacity: 256 CUs x 4 SIMDs x 2.4 GHz.  A wave64 full-rate FP32
-# instruction occupies a SIMD for 2 cycles (the 157.3 TFLOP/s FP32 vector
-# peak); transcendentals and 32x32->64 integer multiplies run at a quarter of
-# that rate (8 cycles; measured 8.9 on the chip).
+# VALU issue capacity: 256 CUs x 4 SIMDs x 2.4 GHz.  Nominal costs: a wave64
+# full-rate FP32 instruction occupies a SIMD for 2 cycles (the 157.3 TFLOP/s
+# FP32 vector peak), a quarter-rate one 8.  The bench prices the kernel with the
+# costs the issue probe measures instead (v_mad_u64_u32 takes about 4).
 SIMD_COUNT = 256 * 4
 SIMD_CYCLES_PER_S = SIMD_COUNT * 2.4e9
 CYCLES_FULL, CYCLES_QUARTER = 2, 8
@@ -63,13 +63,22 @@ def measured_traffic(launch_bytes):
             "algorithmic_bytes": launch_bytes, "calibration": t.get("calibration")}
 
 
-def alu_roofline(particles_per_s, clock=None):
+def measure_issue_costs(kp):
+    """SIMD-cycles per wave64 instruction of the classes the forward kernel
+    issues, measured on this chip (kappa_issue_probe: saturated issue, in-kernel
+    clock, so independent of the clock the chip holds)."""
+    return {name: kp.issue_cost(name)["cycles"] for name in ("fma_f32", "transcendental_f32", "mad_u64_u32")}
+
+
+def alu_roofline(particles_per_s, clock=None, costs=None):
     """VALU-issue roofline of the dominant kernel from its measured instruction
     counts (rocprofv3 SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32 and the static
-    v_mad_u64_u32 count), or None when they were taken on other kernel sources.
-    The peak is the 2.4 GHz one; with `clock` (the core clock measured by the
-    clock probe during the same workload) the fraction of the issue capacity
-    at that clock is added."""
+    v_mad_u64_u32 count), priced with the issue costs measured by the issue
+    probe (`costs`; without them the nominal 2, 8 and 8 SIMD-cycles), or None
+    when the counts were taken on other kernel sources.  The peak is the
+    2.4 GHz one; with `clock` (the core clock measured by the clock probe
+    during the same workload) the fraction of the issue capacity at that
+    clock is added."""
     try:
         with open(VALU_FILE) as f:
             v = json.load(f)
@@ -77,13 +86,17 @@ def alu_roofline(particles_per_s, clock=None):
         return None
     if v.get("kernel_source_sha") != kernel_source_hash():
         return None
-    quarter = v["trans_per_particle"] + v["mad_u64_per_particle"]
-    full = v["valu_per_particle"] - quarter
-    cycles_per_particle = (CYCLES_FULL * full + CYCLES_QUARTER * quarter) / 64.0
+    c = costs or {"fma_f32": CYCLES_FULL, "transcendental_f32": CYCLES_QUARTER, "mad_u64_u32": CYCLES_QUARTER}
+    trans, mad = v["trans_per_particle"], v["mad_u64_per_particle"]
+    full = v["valu_per_particle"] - trans - mad
+    cycles_per_particle = (c["fma_f32"] * full + c["transcendental_f32"] * trans + c["mad_u64_u32"] * mad) / 64.0
     achieved = particles_per_s * cycles_per_particle
     out = {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
            "frac": achieved / SIMD_CYCLES_PER_S, "valu_per_particle": v["valu_per_particle"],
-           "quarter_rate_per_particle": quarter, "simd_cycles_per_particle": cycles_per_particle}
+           "per_particle": {"full_rate": full, "transcendental": trans, "mad_u64_u32": mad},
+           "simd_cycles_per_instruction": c,
+           "costs_from": "kappa_issue_probe on this chip" if costs else "nominal rates",
+           "simd_cycles_per_particle": cycles_per_particle}
     if clock:
         at_clock = SIMD_COUNT * clock["core_clock_ghz"] * 1e9
         out.update({"measured_clock": clock, "peak_at_measured_clock": at_clock,
@@ -578,7 +591,9 @@ def main():
     clock = finish_clock_probe(probe, torch, avg_kernel_ms)
     log(f"core clock during the workload: {clock['core_clock_ghz']:.3f} GHz "
         f"(probe launch {clock['probe_launch_ms']:.4f} ms against {avg_kernel_ms:.4f} ms timed)")
-    result["roofline_alu"] = alu_roofline(n / (avg_kernel_ms * 1e-3), clock)
+    costs = measure_issue_costs(kp)
+    log("issue costs (SIMD-cycles per wave64 instruction): " + ", ".join(f"{k} {v:.2f}" for k, v in costs.items()))
+    result["roofline_alu"] = alu_roofline(n / (avg_kernel_ms * 1e-3), clock, costs)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
         log("cpu baseline done")

@@ -369,6 +369,33 @@ KAPPA_API kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n,
                                          void *vz, uint64_t *stamps, uint64_t stamps_len, uint32_t *blocks,
                                          double *wall_hz, void *stream);
 
+/* kappa_issue_probe: issue cost of one gfx950 instruction class, the basis of
+ * the VALU-issue roofline.  One launch in which each wave issues *steps
+ * instructions of the class on 8 independent chains per lane, one round of 8
+ * waves per SIMD:
+ *   op 0 v_fma_f32 (VGPR operands), 1 v_log_f32 (a transcendental),
+ *   2 v_mad_u64_u32, 3 v_fma_f64, 4 v_bitop3_b32 (VGPR operands).
+ * Wave w writes stamps[2w] = core-clock cycles (s_memtime) and stamps[2w+1] =
+ * constant-rate ticks (s_memrealtime, *wall_hz per second) from its start to
+ * its end.  With t the launch's duration, clock = sum(cycles) / sum(ticks) x
+ * *wall_hz and SIMDs = 4 x CUs = *blocks / 2: SIMD-cycles per wave
+ * instruction = SIMDs x clock x t / (4 x *blocks x *steps).
+ *   sink    device floats, at least *blocks x 256, written (keeps the chains live)
+ *   stamps  device uint64, at least *blocks x 8, 8-byte aligned, written
+ *   blocks, steps, wall_hz  host, written (blocks = 8 x CUs) also when the
+ *           buffers are too small (KAPPA_ERANGE), so a first call with zero
+ *           lengths sizes them.
+ * Asynchronous; needs the device (KAPPA_EDEVICE/KAPPA_EUNSUPPORTED otherwise).
+ *
+ * kappa_transcendental_probe: out[i] = the hardware instruction applied to
+ * in[i] (n floats, device, 4-byte aligned): op 0 v_log_f32 (log2), 1
+ * v_exp_f32 (2^x), 2 v_sin_f32 and 3 v_cos_f32 (argument in revolutions), 4
+ * v_sqrt_f32, 5 v_rsq_f32, 6 v_rcp_f32.  Asynchronous. */
+KAPPA_API kappa_status kappa_issue_probe(int op, float *sink, uint64_t sink_len, uint64_t *stamps,
+                                         uint64_t stamps_len, uint32_t *blocks, uint32_t *steps, double *wall_hz,
+                                         void *stream);
+KAPPA_API kappa_status kappa_transcendental_probe(int op, const float *in, float *out, uint64_t n, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 KAPPA_API const char *kappa_status_string(kappa_status status);
 

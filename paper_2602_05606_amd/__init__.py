@@ -18,7 +18,8 @@ from ._lib import FP32, FP32_NOTAIL, FP64, Cell, KappaError, Segment
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
-    "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
+    "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "issue_cost", "ISSUE_CLASSES",
+    "transcendental_probe", "TRANSCENDENTALS", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
     "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell",
 ]
 
@@ -353,6 +354,65 @@ def clock_probe(kappa, theta, n, seed, *, counter_offset=0, seg_id=0, precision=
 def clock_probe_stamps(n):
     """Entries of a stamps buffer that suffices for clock_probe of n particles."""
     return 4 * max(1, -(-n // 64))
+
+
+ISSUE_CLASSES = {"fma_f32": 0, "transcendental_f32": 1, "mad_u64_u32": 2, "fma_f64": 3, "bitop3_b32": 4}
+
+
+def issue_cost(op, reps=5, device=None, stream=None):
+    """SIMD-cycles per wave64 instruction of one instruction class
+    (kappa_issue_probe; op a key or value of ISSUE_CLASSES), from reps
+    back-to-back launches timed with events and the core clock of the last
+    one.  Returns {"cycles": ..., "clock_ghz": ...}."""
+    torch = _torch()
+    op = ISSUE_CLASSES.get(op, op)
+    lib = _lib.load()
+    blocks, steps, hz = ctypes.c_uint32(0), ctypes.c_uint32(0), ctypes.c_double(0.0)
+    st = lib.kappa_issue_probe(op, None, 0, None, 0, ctypes.byref(blocks), ctypes.byref(steps), ctypes.byref(hz),
+                               None)
+    if st != _lib.ERANGE:
+        _lib.check(st, "kappa_issue_probe")
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    sink = torch.empty(blocks.value * 256, dtype=torch.float32, device=dev)
+    stamps = torch.empty(blocks.value * 8, dtype=torch.int64, device=dev)
+    s = _stream(stream, dev)
+
+    def launch():
+        _lib.check(lib.kappa_issue_probe(op, _ptr(sink), sink.numel(), _ptr(stamps), stamps.numel(),
+                                         ctypes.byref(blocks), ctypes.byref(steps), ctypes.byref(hz), s),
+                   "kappa_issue_probe")
+
+    for _ in range(2):
+        launch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        launch()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    h = stamps.cpu()
+    clock = int(h[0::2].sum()) / int(h[1::2].sum()) * hz.value
+    simds = blocks.value // 2  # 8 workgroups per CU, 4 SIMDs per CU
+    return {"cycles": simds * clock * sec / (4 * blocks.value * steps.value), "clock_ghz": clock / 1e9}
+
+
+TRANSCENDENTALS = {"log2": 0, "exp2": 1, "sin_rev": 2, "cos_rev": 3, "sqrt": 4, "rsq": 5, "rcp": 6}
+
+
+def transcendental_probe(op, x, out=None, stream=None):
+    """The gfx950 hardware instruction applied to each element of the float32
+    device tensor x (kappa_transcendental_probe; op a key or value of
+    TRANSCENDENTALS; sin_rev and cos_rev take revolutions)."""
+    torch = _torch()
+    op = TRANSCENDENTALS.get(op, op)
+    x = x.contiguous()
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    out = torch.empty_like(x) if out is None else out
+    _lib.check(_lib.load().kappa_transcendental_probe(op, _ptr(x), _ptr(out), x.numel(), _stream(stream, x.device)),
+               "kappa_transcendental_probe")
+    return out
 
 
 def core_clock_hz(stamps, wall_hz):

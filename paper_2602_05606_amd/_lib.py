@@ -78,6 +78,9 @@ SIGNATURES = {
     "kappa_optimum_c": (_st, [_vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp]),
     "kappa_fill_probe": (_st, [_u64, _i, _vp, _vp, _vp, _vp]),
     "kappa_copy_probe": (_st, [_vp, _vp, _u64, _vp]),
+    "kappa_issue_probe": (_st, [_i, _vp, _u64, _vp, _u64, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                                ctypes.POINTER(_d), _vp]),
+    "kappa_transcendental_probe": (_st, [_i, _vp, _vp, _u64, _vp]),
     "kappa_clock_probe": (_st, [_d, _d, _u64, _u64, _u64, _u32, _i, _vp, _vp, _vp, _vp, _u64,
                                 ctypes.POINTER(_u32), ctypes.POINTER(_d), _vp]),
     "kappa_status_string": (ctypes.c_char_p, [_i]),

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkappa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["setup.cpp", "api.hip", "forward.hip", "backward.hip", "batched.hip", "baselines.hip", "histogram.hip",
-           "divergence.hip"]
+           "divergence.hip", "hwprobe.hip"]
 ARCH = "gfx950"
 
 

@@ -404,6 +404,47 @@ kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t bytes, void *
     return check_hip(launch_copy_probe(src, dst, bytes, static_cast<hipStream_t>(stream)), "copy probe launch");
 }
 
+kappa_status kappa_issue_probe(int op, float *sink, uint64_t sink_len, uint64_t *stamps, uint64_t stamps_len,
+                               uint32_t *blocks, uint32_t *steps, double *wall_hz, void *stream)
+{
+    if (!blocks || !steps || !wall_hz) return fail(KAPPA_EINVAL, "null blocks, steps or wall_hz pointer");
+    *blocks = 0;
+    *steps = 0;
+    *wall_hz = 0.0;
+    if (op < 0 || op > 4) return fail(KAPPA_EINVAL, "unknown instruction class %d", op);
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    const uint32_t nb = issue_probe_blocks();
+    *blocks = nb;
+    *steps = static_cast<uint32_t>(issue_probe_steps());
+    if (sink_len < static_cast<uint64_t>(nb) * 256 || stamps_len < static_cast<uint64_t>(nb) * 8)
+        return fail(KAPPA_ERANGE, "the probe needs %u x 256 sink floats and %u x 8 stamps", nb, nb);
+    if (!sink || !stamps) return fail(KAPPA_EINVAL, "null sink or stamps pointer");
+    if (reinterpret_cast<uintptr_t>(sink) % 4 || reinterpret_cast<uintptr_t>(stamps) % 8)
+        return fail(KAPPA_EALIGN, "sink must be 4-byte and stamps 8-byte aligned");
+    int dev = 0, khz = 0;
+    st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != KAPPA_OK) return st;
+    st = check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+    if (st != KAPPA_OK) return st;
+    if (khz <= 0) return fail(KAPPA_EDEVICE, "device reports no constant-rate counter");
+    *wall_hz = 1e3 * khz;
+    return check_hip(launch_issue_probe(op, sink, stamps, static_cast<hipStream_t>(stream)), "issue probe launch");
+}
+
+kappa_status kappa_transcendental_probe(int op, const float *in, float *out, uint64_t n, void *stream)
+{
+    if (op < 0 || op > 6) return fail(KAPPA_EINVAL, "unknown transcendental %d", op);
+    if (n == 0) return KAPPA_OK;
+    if (!in || !out) return fail(KAPPA_EINVAL, "null pointer with n = %llu", (unsigned long long)n);
+    if (reinterpret_cast<uintptr_t>(in) % 4 || reinterpret_cast<uintptr_t>(out) % 4)
+        return fail(KAPPA_EALIGN, "in and out must be 4-byte aligned");
+    kappa_status st = require_device();
+    if (st != KAPPA_OK) return st;
+    return check_hip(launch_transcendental_probe(op, in, out, n, static_cast<hipStream_t>(stream)),
+                     "transcendental probe launch");
+}
+
 // ---- batched --------------------------------------------------------------
 
 static kappa_status validate_segments(const kappa_segment *segs, uint32_t nseg, int precision)

@@ -172,6 +172,20 @@ def test_clock_probe_argument_checks():
                                  None) == _lib.EINVAL
 
 
+def test_hardware_probe_argument_checks():
+    lib = _lib.load()
+    blocks, steps, hz = ctypes.c_uint32(7), ctypes.c_uint32(7), ctypes.c_double(1.0)
+    assert lib.kappa_issue_probe(5, FAKE, 1 << 20, FAKE, 1 << 20, ctypes.byref(blocks), ctypes.byref(steps),
+                                 ctypes.byref(hz), None) == _lib.EINVAL
+    assert blocks.value == 0 and steps.value == 0
+    assert lib.kappa_issue_probe(0, FAKE, 1 << 20, FAKE, 1 << 20, None, ctypes.byref(steps), ctypes.byref(hz),
+                                 None) == _lib.EINVAL
+    assert lib.kappa_transcendental_probe(7, FAKE, FAKE, 16, None) == _lib.EINVAL
+    assert lib.kappa_transcendental_probe(0, None, None, 0, None) == _lib.OK
+    assert lib.kappa_transcendental_probe(0, None, FAKE, 16, None) == _lib.EINVAL
+    assert lib.kappa_transcendental_probe(0, FAKE_ODD, FAKE, 16, None) == _lib.EALIGN
+
+
 def test_clock_probe_needs_one_launch(monkeypatch):
     # with at most 4 workgroups per launch, 2^20 particles need several launches,
     # which the probe (one launch, one stamp per workgroup) refuses
