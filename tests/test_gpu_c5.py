@@ -86,7 +86,8 @@ def test_c5_precision_and_tail(orc):
               "tail_particles_in_1e9": int(len(tails)), "expected_tail_particles": c["n"] * 2.0 ** -20,
               "fp32_vs_oracle_fp64": e32, "fp64_vs_oracle_fp64": e64,
               "ks_speed_fp32_vs_oracle_fp64": ks32, "ks_speed_fp64_vs_oracle_fp64": ks64,
-              "fp32_max_norm_relative_error": float(d.max()), "fp32_mean_norm_relative_error": float(d.mean())}
+              "fp32_max_norm_relative_error": float(d.max()), "fp32_mean_norm_relative_error": float(d.mean()),
+              "command": "KAPPA_REPORT_DIR=<dir> python -m pytest -s tests/test_gpu_c5.py (from the repository root)"}
     print(json.dumps(report, indent=1, default=float))
     if os.environ.get("KAPPA_REPORT_DIR"):
         with open(os.path.join(os.environ["KAPPA_REPORT_DIR"], "c5_report.json"), "w") as f:
