@@ -356,7 +356,8 @@ def clock_probe_stamps(n):
     return 4 * max(1, -(-n // 64))
 
 
-ISSUE_CLASSES = {"fma_f32": 0, "transcendental_f32": 1, "mad_u64_u32": 2, "fma_f64": 3, "bitop3_b32": 4}
+ISSUE_CLASSES = {"fma_f32": 0, "transcendental_f32": 1, "mad_u64_u32": 2, "fma_f64": 3, "bitop3_b32": 4,
+                 "log_plus_3fma_f32": 5}
 
 
 def issue_cost(op, reps=5, device=None, stream=None):

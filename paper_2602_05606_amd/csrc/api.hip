@@ -411,12 +411,12 @@ kappa_status kappa_issue_probe(int op, float *sink, uint64_t sink_len, uint64_t 
     *blocks = 0;
     *steps = 0;
     *wall_hz = 0.0;
-    if (op < 0 || op > 4) return fail(KAPPA_EINVAL, "unknown instruction class %d", op);
+    if (op < 0 || op > 5) return fail(KAPPA_EINVAL, "unknown instruction class %d", op);
     kappa_status st = require_device();
     if (st != KAPPA_OK) return st;
     const uint32_t nb = issue_probe_blocks();
     *blocks = nb;
-    *steps = static_cast<uint32_t>(issue_probe_steps());
+    *steps = static_cast<uint32_t>(issue_probe_steps(op));
     if (sink_len < static_cast<uint64_t>(nb) * 256 || stamps_len < static_cast<uint64_t>(nb) * 8)
         return fail(KAPPA_ERANGE, "the probe needs %u x 256 sink floats and %u x 8 stamps", nb, nb);
     if (!sink || !stamps) return fail(KAPPA_EINVAL, "null sink or stamps pointer");

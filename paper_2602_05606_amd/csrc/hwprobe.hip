@@ -16,19 +16,22 @@ constexpr int kIssueChains = 8;
 // waves per CU, all resident at once), so the issue port, not latency, sets
 // the pace, and the launch is long against its ramp.  Wave w records its
 // core-clock cycles (s_memtime) and constant-rate ticks (s_memrealtime) from
-// start to end.
+// start to end.  Class 5 mixes kinds: each chain step is one v_log_f32 on one
+// register and three dependent v_fma_f32 on another, four instructions, to see
+// whether the transcendental unit runs beside full-rate work.
 template <int OP>
 __global__ void __launch_bounds__(256) issue_kernel(float *sink, uint64_t *stamps)
 {
     const uint64_t c0 = __builtin_amdgcn_s_memtime();
     const uint64_t r0 = __builtin_amdgcn_s_memrealtime();
     const uint32_t t = threadIdx.x;
-    float f[kIssueChains], fa[kIssueChains], fb[kIssueChains];
+    float f[kIssueChains], g[kIssueChains], fa[kIssueChains], fb[kIssueChains];
     double d[kIssueChains], da[kIssueChains];
     uint32_t u[kIssueChains], w[kIssueChains];
 #pragma unroll
     for (int c = 0; c < kIssueChains; ++c) {
         f[c] = 1.0f + 0.001f * static_cast<float>((t + c) & 31);
+        g[c] = f[c];
         fa[c] = 0.999f - 1e-6f * static_cast<float>(t & 7);
         fb[c] = 1e-4f * static_cast<float>((t >> 3) & 3) + 1e-5f * static_cast<float>(c);
         d[c] = f[c];
@@ -44,11 +47,17 @@ __global__ void __launch_bounds__(256) issue_kernel(float *sink, uint64_t *stamp
             if constexpr (OP == 2) u[c] = static_cast<uint32_t>((static_cast<uint64_t>(u[c]) * 0xD2511F53u + w[c]) >> 32);
             if constexpr (OP == 3) d[c] = __builtin_fma(d[c], da[c], static_cast<double>(fb[c]));
             if constexpr (OP == 4) u[c] = __builtin_amdgcn_bitop3_b32(u[c], w[c], w[(c + 4) % kIssueChains], 0x96);
+            if constexpr (OP == 5) {
+                f[c] = __builtin_amdgcn_logf(f[c]);
+                g[c] = __builtin_fmaf(g[c], fa[c], fb[c]);
+                g[c] = __builtin_fmaf(g[c], fa[c], 0.5f * fb[c]);
+                g[c] = __builtin_fmaf(g[c], fa[c], 0.25f * fb[c]);
+            }
         }
     }
     float s = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kIssueChains; ++c) s += f[c] + static_cast<float>(d[c]) + static_cast<float>(u[c]);
+    for (int c = 0; c < kIssueChains; ++c) s += f[c] + g[c] + static_cast<float>(d[c]) + static_cast<float>(u[c]);
     sink[static_cast<uint64_t>(blockIdx.x) * blockDim.x + t] = s;
     const uint64_t c1 = __builtin_amdgcn_s_memtime();
     const uint64_t r1 = __builtin_amdgcn_s_memrealtime();
@@ -81,7 +90,7 @@ __global__ void __launch_bounds__(256) transcendental_kernel(int op, const float
 
 }  // namespace
 
-int issue_probe_steps() { return kIssueIters * kIssueChains; }
+int issue_probe_steps(int op) { return kIssueIters * kIssueChains * (op == 5 ? 4 : 1); }
 
 uint32_t issue_probe_blocks() { return static_cast<uint32_t>(device_cu_count()) * 8u; }
 
@@ -94,6 +103,7 @@ hipError_t launch_issue_probe(int op, float *sink, uint64_t *stamps, hipStream_t
     case 2: hipLaunchKernelGGL(issue_kernel<2>, grid, block, 0, stream, sink, stamps); break;
     case 3: hipLaunchKernelGGL(issue_kernel<3>, grid, block, 0, stream, sink, stamps); break;
     case 4: hipLaunchKernelGGL(issue_kernel<4>, grid, block, 0, stream, sink, stamps); break;
+    case 5: hipLaunchKernelGGL(issue_kernel<5>, grid, block, 0, stream, sink, stamps); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -60,7 +60,7 @@ hipError_t launch_philox(uint64_t n, uint64_t counter_offset, uint32_t seg, uint
 hipError_t launch_fill_probe(int mode, uint64_t n, void *vx, void *vy, void *vz, hipStream_t stream);
 hipError_t launch_copy_probe(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 // Hardware probes (hwprobe.hip): instruction issue cost and transcendental accuracy.
-int issue_probe_steps();
+int issue_probe_steps(int op);
 uint32_t issue_probe_blocks();
 hipError_t launch_issue_probe(int op, float *sink, uint64_t *stamps, hipStream_t stream);
 hipError_t launch_transcendental_probe(int op, const float *in, float *out, uint64_t n, hipStream_t stream);

@@ -4,6 +4,10 @@ VALU-issue roofline rest on.
 * issue costs (kappa_issue_probe, SIMD-cycles per wave64 instruction at
   saturation, clock-independent): v_fma_f32 about 2, a transcendental about
   8, v_mad_u64_u32 about 4, v_fma_f64 about 4, v_bitop3_b32 about 2;
+* a stream mixing one transcendental with three v_fma_f32 costs at least the
+  sum of the two classes' separate costs: the transcendental unit does not
+  run beside full-rate work, so a transcendental taken off the path saves
+  its whole cost;
 * accuracy of the hardware transcendentals the FP32 inversion uses
   (kappa_transcendental_probe) against float64 references: v_log_f32 within
   2 ulp of its result, also next to 1 where log2 x is small; v_exp_f32,
@@ -28,6 +32,13 @@ def test_issue_costs(op, lo, hi):
     print(f"{op}: {r['cycles']:.3f} SIMD-cycles per wave64 instruction at {r['clock_ghz']:.3f} GHz")
     assert lo < r["cycles"] < hi
     assert 0.3 < r["clock_ghz"] < 2.45
+
+
+def test_transcendental_does_not_overlap_full_rate_work():
+    fma, log = kp.issue_cost("fma_f32")["cycles"], kp.issue_cost("transcendental_f32")["cycles"]
+    mixed = 4 * kp.issue_cost("log_plus_3fma_f32")["cycles"]  # per step of 1 log + 3 fma
+    print(f"1 log + 3 fma: {mixed:.2f} SIMD-cycles against {log:.2f} + 3 x {fma:.2f} = {log + 3 * fma:.2f} apart")
+    assert mixed > 0.95 * (log + 3 * fma)
 
 
 def _run(op, x):
