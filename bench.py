@@ -567,6 +567,23 @@ def main():
                 plan.graph_launch(outb)
             torch.cuda.synchronize()
             wall_ms = (time.perf_counter() - t0) * 1e3 / 50
+            # the plan's launch as nodes of a caller's graph (a PIC step captures its whole
+            # step): 8 launches into 8 output sets per replay, so hipGraphLaunch's host
+            # cost is paid once per 8 kernels
+            caller_bufs = [plan.outputs() for _ in range(8)]
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for b in caller_bufs:
+                    plan.launch(b)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            caller_graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(caller_graph):
+                for b in caller_bufs:
+                    plan.launch(b)
+            caller_ms = time_launches(caller_graph.replay, 10, torch) / len(caller_bufs)
+            del caller_graph, caller_bufs
             # the single-species kernel on the same number of particles, for comparison
             single_ms = time_launches(lambda: kp.sample(3.0, 1.0, plan.total, 4, precision=kp.FP32, out=outb), 20,
                                       torch)
@@ -580,6 +597,8 @@ def main():
             extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
                                     "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
                                     "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),
+                                    "in_caller_graph_ms_per_launch": caller_ms,
+                                    "in_caller_graph_particles_per_s": plan.total / (caller_ms * 1e-3),
                                     "single_species_same_size_ms": single_ms,
                                     "pic_positions_and_velocities": {
                                         "direct_launch_ms": pic_ms, "graph_launch_ms": pic_graph_ms,
