@@ -37,6 +37,16 @@
  *            Arguments are validated before any HIP call.  A HIP failure
  *            returns KAPPA_EDEVICE and kappa_last_error() gives the message.
  *   device   the current HIP device must be gfx950, else KAPPA_EUNSUPPORTED.
+ *   threads  entry points that take no plan keep no state between calls but
+ *            the calling thread's last-error message and a lock-guarded
+ *            per-device cache of the CU count: any number of host threads
+ *            may call them at once, on any streams.  A plan is not
+ *            thread-safe: calls on one plan must not overlap in time (they
+ *            share its captured graph and launch shape).  Its launches may be
+ *            in flight on several streams at once, into different outputs.
+ *   capture  kappa_sample, kappa_sample_backward and the plan launches
+ *            (direct, not graph) allocate, synchronise and memset nothing, so
+ *            a caller may capture them into a hipGraph of its own.
  */
 #ifndef KAPPA_H
 #define KAPPA_H
