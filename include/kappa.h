@@ -30,7 +30,11 @@
  *            the caller, written and never read.  double for KAPPA_FP64,
  *            float for KAPPA_FP32 and KAPPA_FP32_NOTAIL.  Each pointer must be
  *            aligned to its element size (else KAPPA_EALIGN); 16-byte aligned
- *            pointers take the vector-store path.
+ *            pointers take the vector-store path.  kappa_sample also takes it
+ *            for three views at one common misalignment (slices of aligned
+ *            arrays) of at least 2^16 particles, after writing the particles
+ *            before the 16-byte boundary one per thread in a launch of their
+ *            own.
  *   stream   a hipStream_t passed as void*; NULL is the legacy default stream.
  *            Calls are asynchronous on the stream unless stated otherwise.
  *   errors   return codes only; nothing aborts or throws across the ABI.

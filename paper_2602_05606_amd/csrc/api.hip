@@ -79,6 +79,19 @@ bool vec_aligned(int precision, const void *vx, const void *vy, const void *vz)
            reinterpret_cast<uintptr_t>(vz) % 16 == 0;
 }
 
+// Particles to write one per thread before three views that share one
+// misalignment reach a 16-byte boundary together, when the rest is long
+// enough to pay for a second launch; 0 otherwise (aligned views, views at
+// different misalignments, short calls).
+uint64_t peel_head(int precision, uint64_t n, const void *vx, const void *vy, const void *vz)
+{
+    constexpr uint64_t kPeelMin = 1u << 16;
+    const uintptr_t m = reinterpret_cast<uintptr_t>(vx) % 16;
+    if (m == 0 || m != reinterpret_cast<uintptr_t>(vy) % 16 || m != reinterpret_cast<uintptr_t>(vz) % 16) return 0;
+    const uint64_t head = (16 - m) / (precision == KAPPA_FP64 ? 8 : 4);
+    return n >= kPeelMin + head ? head : 0;
+}
+
 FwdArgs forward_args(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id,
                      void *vx, void *vy, void *vz)
 {
@@ -181,9 +194,27 @@ kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed,
     st = require_device();
     if (st != KAPPA_OK) return st;
     const FwdArgs a = forward_args(kappa, theta, n, seed, counter_offset, seg_id, vx, vy, vz);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t head = peel_head(precision, n, vx, vy, vz);
+    if (head > 0) {
+        // a view at a common misalignment (a slice of three aligned arrays):
+        // the first particles up to the 16-byte boundary one per thread, the
+        // rest with vector stores; the output depends only on the counters
+        FwdArgs h = a, b = a;
+        h.n = head;
+        const size_t esz = precision == KAPPA_FP64 ? 8 : 4;
+        b.n = n - head;
+        b.counter_offset = counter_offset + head;
+        b.vx = static_cast<char *>(vx) + head * esz;
+        b.vy = static_cast<char *>(vy) + head * esz;
+        b.vz = static_cast<char *>(vz) + head * esz;
+        st = check_hip(launch_forward(precision, forward_shape(precision, head, false), false, h, s), "forward kernel launch");
+        if (st != KAPPA_OK) return st;
+        return check_hip(launch_forward(precision, forward_shape(precision, b.n, true), true, b, s), "forward kernel launch");
+    }
     const bool vec = vec_aligned(precision, vx, vy, vz);
     const Shape shape = forward_shape(precision, n, vec);
-    return check_hip(launch_forward(precision, shape, vec, a, static_cast<hipStream_t>(stream)), "forward kernel launch");
+    return check_hip(launch_forward(precision, shape, vec, a, s), "forward kernel launch");
 }
 
 kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,

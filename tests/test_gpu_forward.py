@@ -160,19 +160,24 @@ def test_determinism_and_chunking():
         assert bits_equal(a, tuple(np.concatenate([x, y]) for x, y in zip(c1, c2)))
 
 
-def test_store_path_invariance():
-    """Misaligned outputs take the one-particle-per-thread path; results are
-    bit-identical to the 16-byte vector-store path."""
-    n = 100_000
-    for precision in (kp.FP64, kp.FP32):
-        dt = torch.float64 if precision == kp.FP64 else torch.float32
-        base = [torch.empty(n + 1, dtype=dt, device="cuda") for _ in range(3)]
-        mis = tuple(t[1:] for t in base)
-        assert all(t.data_ptr() % 16 != 0 for t in mis)
-        kp.sample(4.0, 1.0, n, 3, precision=precision, out=mis)
-        ref = kp.sample(4.0, 1.0, n, 3, precision=precision)
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
+@pytest.mark.parametrize("n", [1000, 65_539, 100_000, 1_000_003])
+def test_store_path_invariance(precision, n):
+    """Outputs at any element offset give the bits of 16-byte aligned ones:
+    views sharing one misalignment write the particles up to the 16-byte
+    boundary one per thread and the rest with vector stores (from 2^16 + head
+    particles on; one-per-thread below), and views at different
+    misalignments take the one-per-thread path throughout."""
+    dt = torch.float64 if precision == kp.FP64 else torch.float32
+    ref = to_host(*kp.sample(4.0, 1.0, n, 3, counter_offset=9, precision=precision))
+    per16 = 16 // (8 if precision == kp.FP64 else 4)
+    offsets = [(o, o, o) for o in range(1, per16)] + [(1, 0, per16 - 1)]
+    for offs in offsets:
+        views = tuple(torch.empty(n + per16, dtype=dt, device="cuda")[o:o + n] for o in offs)
+        assert [v.data_ptr() % 16 for v in views] == [o * (16 // per16) for o in offs]
+        kp.sample(4.0, 1.0, n, 3, counter_offset=9, precision=precision, out=views)
         torch.cuda.synchronize()
-        assert bits_equal(to_host(*mis), to_host(*ref))
+        assert bits_equal(to_host(*views), ref), offs
 
 
 def test_seg_id_selects_independent_stream(orc):
