@@ -67,7 +67,8 @@ def measure_issue_costs(kp):
     """SIMD-cycles per wave64 instruction of the classes the forward kernel
     issues, measured on this chip (kappa_issue_probe: saturated issue, in-kernel
     clock, so independent of the clock the chip holds)."""
-    return {name: kp.issue_cost(name)["cycles"] for name in ("fma_f32", "transcendental_f32", "mad_u64_u32")}
+    return {name: kp.issue_cost(name)["cycles"]
+            for name in ("fma_f32", "transcendental_f32", "mad_u64_u32", "fma_f32_literal")}
 
 
 def alu_roofline(particles_per_s, clock=None, costs=None):
@@ -75,7 +76,10 @@ def alu_roofline(particles_per_s, clock=None, costs=None):
     counts (rocprofv3 SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32 and the static
     v_mad_u64_u32 count), priced with the issue costs measured by the issue
     probe (`costs`; without them the nominal 2, 8 and 8 SIMD-cycles), or None
-    when the counts were taken on other kernel sources.  The peak is the
+    when the counts were taken on other kernel sources.  Full-rate
+    instructions are priced as v_fma_f32 with three VGPR operands; with the
+    probe's literal-operand v_fma_f32 as well, the range between the two
+    prices is reported too.  The peak is the
     2.4 GHz one; with `clock` (the core clock measured by the clock probe
     during the same workload) the fraction of the issue capacity at that
     clock is added."""
@@ -97,10 +101,17 @@ def alu_roofline(particles_per_s, clock=None, costs=None):
            "simd_cycles_per_instruction": c,
            "costs_from": "kappa_issue_probe on this chip" if costs else "nominal rates",
            "simd_cycles_per_particle": cycles_per_particle}
+    low = None
+    if "fma_f32_literal" in c:
+        # the full-rate price with a literal operand (no three-VGPR operand reads): the low end
+        low = (c["fma_f32_literal"] * full + c["transcendental_f32"] * trans + c["mad_u64_u32"] * mad) / 64.0
+        out["simd_cycles_per_particle_range"] = [low, cycles_per_particle]
     if clock:
         at_clock = SIMD_COUNT * clock["core_clock_ghz"] * 1e9
         out.update({"measured_clock": clock, "peak_at_measured_clock": at_clock,
                     "frac_at_measured_clock": achieved / at_clock})
+        if low is not None:
+            out["frac_at_measured_clock_range"] = [particles_per_s * low / at_clock, achieved / at_clock]
     return out
 
 

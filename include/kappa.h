@@ -391,7 +391,8 @@ KAPPA_API kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n,
  *   2 v_mad_u64_u32, 3 v_fma_f64, 4 v_bitop3_b32 (VGPR operands),
  *   5 a mix: per chain step one v_log_f32 and three v_fma_f32 on another
  *     register (4 instructions, all counted in *steps), whose cost against
- *     the sum of classes 0 and 1 shows whether the two kinds overlap.
+ *     the sum of classes 0 and 1 shows whether the two kinds overlap,
+ *   6 v_fma_f32 with two VGPR operands and a literal constant.
  * Wave w writes stamps[2w] = core-clock cycles (s_memtime) and stamps[2w+1] =
  * constant-rate ticks (s_memrealtime, *wall_hz per second) from its start to
  * its end.  With t the launch's duration, clock = sum(cycles) / sum(ticks) x

@@ -357,7 +357,7 @@ def clock_probe_stamps(n):
 
 
 ISSUE_CLASSES = {"fma_f32": 0, "transcendental_f32": 1, "mad_u64_u32": 2, "fma_f64": 3, "bitop3_b32": 4,
-                 "log_plus_3fma_f32": 5}
+                 "log_plus_3fma_f32": 5, "fma_f32_literal": 6}
 
 
 def issue_cost(op, reps=5, device=None, stream=None):

@@ -442,7 +442,7 @@ kappa_status kappa_issue_probe(int op, float *sink, uint64_t sink_len, uint64_t 
     *blocks = 0;
     *steps = 0;
     *wall_hz = 0.0;
-    if (op < 0 || op > 5) return fail(KAPPA_EINVAL, "unknown instruction class %d", op);
+    if (op < 0 || op > 6) return fail(KAPPA_EINVAL, "unknown instruction class %d", op);
     kappa_status st = require_device();
     if (st != KAPPA_OK) return st;
     const uint32_t nb = issue_probe_blocks();

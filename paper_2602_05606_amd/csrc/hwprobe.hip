@@ -18,7 +18,8 @@ constexpr int kIssueChains = 8;
 // core-clock cycles (s_memtime) and constant-rate ticks (s_memrealtime) from
 // start to end.  Class 5 mixes kinds: each chain step is one v_log_f32 on one
 // register and three dependent v_fma_f32 on another, four instructions, to see
-// whether the transcendental unit runs beside full-rate work.
+// whether the transcendental unit runs beside full-rate work.  Class 6 is
+// v_fma_f32 with two VGPR operands and a literal, class 0 with three VGPRs.
 template <int OP>
 __global__ void __launch_bounds__(256) issue_kernel(float *sink, uint64_t *stamps)
 {
@@ -47,6 +48,7 @@ __global__ void __launch_bounds__(256) issue_kernel(float *sink, uint64_t *stamp
             if constexpr (OP == 2) u[c] = static_cast<uint32_t>((static_cast<uint64_t>(u[c]) * 0xD2511F53u + w[c]) >> 32);
             if constexpr (OP == 3) d[c] = __builtin_fma(d[c], da[c], static_cast<double>(fb[c]));
             if constexpr (OP == 4) u[c] = __builtin_amdgcn_bitop3_b32(u[c], w[c], w[(c + 4) % kIssueChains], 0x96);
+            if constexpr (OP == 6) f[c] = __builtin_fmaf(f[c], fa[c], 0x1p-14f);
             if constexpr (OP == 5) {
                 f[c] = __builtin_amdgcn_logf(f[c]);
                 g[c] = __builtin_fmaf(g[c], fa[c], fb[c]);
@@ -104,6 +106,7 @@ hipError_t launch_issue_probe(int op, float *sink, uint64_t *stamps, hipStream_t
     case 3: hipLaunchKernelGGL(issue_kernel<3>, grid, block, 0, stream, sink, stamps); break;
     case 4: hipLaunchKernelGGL(issue_kernel<4>, grid, block, 0, stream, sink, stamps); break;
     case 5: hipLaunchKernelGGL(issue_kernel<5>, grid, block, 0, stream, sink, stamps); break;
+    case 6: hipLaunchKernelGGL(issue_kernel<6>, grid, block, 0, stream, sink, stamps); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -175,7 +175,7 @@ def test_clock_probe_argument_checks():
 def test_hardware_probe_argument_checks():
     lib = _lib.load()
     blocks, steps, hz = ctypes.c_uint32(7), ctypes.c_uint32(7), ctypes.c_double(1.0)
-    assert lib.kappa_issue_probe(6, FAKE, 1 << 20, FAKE, 1 << 20, ctypes.byref(blocks), ctypes.byref(steps),
+    assert lib.kappa_issue_probe(7, FAKE, 1 << 20, FAKE, 1 << 20, ctypes.byref(blocks), ctypes.byref(steps),
                                  ctypes.byref(hz), None) == _lib.EINVAL
     assert lib.kappa_issue_probe(-1, FAKE, 1 << 20, FAKE, 1 << 20, ctypes.byref(blocks), ctypes.byref(steps),
                                  ctypes.byref(hz), None) == _lib.EINVAL

@@ -22,3 +22,21 @@ def test_sup_G_minus_F_against_the_oracle(orc, kappa):
     got = bench.sup_G_minus_F(kp, kappa)
     # the bench's grid is 10x denser: it can only find a slightly larger supremum
     assert ref * (1 - 1e-9) <= got <= ref * 1.01
+
+
+def test_alu_roofline_prices_and_range():
+    """The VALU-issue roofline: instruction counts of the committed counter run
+    priced per class; the literal-operand FMA price gives the low end of the
+    range, the three-VGPR price the reported figure."""
+    costs = {"fma_f32": 2.4, "transcendental_f32": 8.4, "mad_u64_u32": 4.6, "fma_f32_literal": 2.1}
+    r = bench.alu_roofline(3.5e11, {"core_clock_ghz": 2.0}, costs)
+    assert r is not None, "the committed VALU counts were taken on other kernel sources"
+    pp = r["per_particle"]
+    want = (2.4 * pp["full_rate"] + 8.4 * pp["transcendental"] + 4.6 * pp["mad_u64_u32"]) / 64
+    assert abs(r["simd_cycles_per_particle"] - want) < 1e-12
+    lo, hi = r["simd_cycles_per_particle_range"]
+    assert lo < hi == r["simd_cycles_per_particle"]
+    f_lo, f_hi = r["frac_at_measured_clock_range"]
+    assert f_hi == r["frac_at_measured_clock"] and f_lo < f_hi
+    assert abs(f_hi - 3.5e11 * want / (1024 * 2.0e9)) < 1e-12
+    assert abs(r["frac"] - 3.5e11 * want / bench.SIMD_CYCLES_PER_S) < 1e-12

@@ -2,7 +2,8 @@
 VALU-issue roofline rest on.
 
 * issue costs (kappa_issue_probe, SIMD-cycles per wave64 instruction at
-  saturation, clock-independent): v_fma_f32 about 2, a transcendental about
+  saturation, clock-independent): v_fma_f32 about 2 (with three VGPR operands
+  or with a literal), a transcendental about
   8, v_mad_u64_u32 about 4, v_fma_f64 about 4, v_bitop3_b32 about 2;
 * a stream mixing one transcendental with three v_fma_f32 costs at least the
   sum of the two classes' separate costs: the transcendental unit does not
@@ -26,7 +27,8 @@ ULP = 2.0 ** -23  # float ulp relative to the value, at most
 
 
 @pytest.mark.parametrize("op,lo,hi", [("fma_f32", 1.8, 2.8), ("transcendental_f32", 6.5, 10.0),
-                                      ("mad_u64_u32", 3.5, 6.5), ("fma_f64", 3.5, 5.5), ("bitop3_b32", 1.8, 3.0)])
+                                      ("mad_u64_u32", 3.5, 6.5), ("fma_f64", 3.5, 5.5), ("bitop3_b32", 1.8, 3.0),
+                                      ("fma_f32_literal", 1.8, 2.8)])
 def test_issue_costs(op, lo, hi):
     r = kp.issue_cost(op)
     print(f"{op}: {r['cycles']:.3f} SIMD-cycles per wave64 instruction at {r['clock_ghz']:.3f} GHz")
