@@ -40,3 +40,11 @@ def test_alu_roofline_prices_and_range():
     assert f_hi == r["frac_at_measured_clock"] and f_lo < f_hi
     assert abs(f_hi - 3.5e11 * want / (1024 * 2.0e9)) < 1e-12
     assert abs(r["frac"] - 3.5e11 * want / bench.SIMD_CYCLES_PER_S) < 1e-12
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr and res.stdout == ""
