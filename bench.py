@@ -608,6 +608,7 @@ def main():
             extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
                                     "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
                                     "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),
+                                    "direct_launch_particles_per_s": plan.total / (direct_ms * 1e-3),
                                     "in_caller_graph_ms_per_launch": caller_ms,
                                     "in_caller_graph_particles_per_s": plan.total / (caller_ms * 1e-3),
                                     "single_species_same_size_ms": single_ms,
