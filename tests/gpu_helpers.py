@@ -23,3 +23,23 @@ def norm_rel_err(g, r):
 
 def bits_equal(a, b):
     return all(np.array_equal(x.view(np.uint8), y.view(np.uint8)) for x, y in zip(a, b))
+
+
+def moments(vx, vy, vz):
+    """Mean, variance and fourth central moment of each component and of v^2."""
+    s2 = vx * vx + vy * vy + vz * vz
+    out = {}
+    for name, c in (("vx", vx), ("vy", vy), ("vz", vz), ("v2", s2)):
+        m1 = c.mean()
+        out[name] = {"mean": m1, "var": ((c - m1) ** 2).mean(), "m4": ((c - m1) ** 4).mean()}
+    return out
+
+
+def rel_errors(a, b):
+    """Relative errors of var and m4; the error of a mean (near zero for the
+    components) is expressed relative to the standard deviation."""
+    out = {}
+    for k in a:
+        out[k] = {"mean_over_std": abs(a[k]["mean"] - b[k]["mean"]) / np.sqrt(b[k]["var"]),
+                  "var": abs(a[k]["var"] / b[k]["var"] - 1), "m4": abs(a[k]["m4"] / b[k]["m4"] - 1)}
+    return out

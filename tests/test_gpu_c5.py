@@ -19,28 +19,10 @@ import torch
 
 import paper_2602_05606_amd as kp
 import workloads
+from gpu_helpers import moments, rel_errors
 
 pytestmark = pytest.mark.gpu
 STRIDE = 100
-
-
-def moments(vx, vy, vz):
-    s2 = vx * vx + vy * vy + vz * vz
-    out = {}
-    for name, c in (("vx", vx), ("vy", vy), ("vz", vz), ("v2", s2)):
-        m1 = c.mean()
-        out[name] = {"mean": m1, "var": ((c - m1) ** 2).mean(), "m4": ((c - m1) ** 4).mean()}
-    return out
-
-
-def rel_errors(a, b):
-    """Relative errors of var and m4; the error of a mean (near zero for the
-    components) is expressed relative to the standard deviation."""
-    out = {}
-    for k in a:
-        out[k] = {"mean_over_std": abs(a[k]["mean"] - b[k]["mean"]) / np.sqrt(b[k]["var"]),
-                  "var": abs(a[k]["var"] / b[k]["var"] - 1), "m4": abs(a[k]["m4"] / b[k]["m4"] - 1)}
-    return out
 
 
 def ks_paired(x, y):
