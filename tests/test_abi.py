@@ -257,3 +257,14 @@ def test_optimum_argument_checks():
     assert opt(FAKE, 4, None, 10, 40, FAKE, None, None) == _lib.EINVAL
     assert opt(FAKE, 4, FAKE, 10, 40, ctypes.c_void_p(0x10004), None, None) == _lib.EALIGN
     assert opt(None, 0, None, 0, 40, None, None, None) == _lib.OK
+
+
+def test_no_fallback_without_the_library(monkeypatch, tmp_path):
+    """Every call goes through libkappa.so: without it the binding raises
+    instead of computing anything on the host."""
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libkappa.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        kp.params(3.0)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        kp.version()
