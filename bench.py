@@ -560,7 +560,14 @@ def main():
                                                          g[2], precision=kp.FP32, workspace=ws), 20, torch)
         extras["backward_c3"] = {"particles_per_s": c3["n"] / (bw_ms * 1e-3), "ms": bw_ms,
                                  "GB_per_s_read": 12 * c3["n"] / (bw_ms * 1e-3) / 1e9}
+        # the same backward in FP64 (FP64 upstream gradient, FP64 inversion throughout)
+        g64 = g.double()
         del g
+        bw64_ms = time_launches(lambda: kp.sample_backward(c3["kappa"], c3["theta"], c3["n"], c3["seed"], g64[0],
+                                                           g64[1], g64[2], precision=kp.FP64, workspace=ws), 10, torch)
+        extras["backward_c3"]["fp64"] = {"particles_per_s": c3["n"] / (bw64_ms * 1e-3), "ms": bw64_ms,
+                                         "GB_per_s_read": 24 * c3["n"] / (bw64_ms * 1e-3) / 1e9}
+        del g64
         log("backward done")
     if "batched" in chosen:
         segs = workloads.batched_segments()
