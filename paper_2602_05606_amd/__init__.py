@@ -20,7 +20,7 @@ __all__ = [
     "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
     "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "issue_cost", "ISSUE_CLASSES",
     "transcendental_probe", "TRANSCENDENTALS", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
-    "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell",
+    "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell", "SEGMENT_DTYPE", "segment_table",
 ]
 
 
@@ -159,9 +159,44 @@ def philox(n, seed, counter_offset=0, seg_id=0, draw=0, device=None, stream=None
     return out
 
 
+def _segment_dtype():
+    import numpy as np
+    return np.dtype([("kappa", "<f8"), ("theta", "<f8"), ("drift", "<f8", (3,)), ("count", "<u8"),
+                     ("seg_id", "<u4"), ("reserved", "<u4")], align=True)
+
+
+def __getattr__(name):
+    if name == "SEGMENT_DTYPE":  # numpy is imported only when the table form is used
+        return _segment_dtype()
+    raise AttributeError(name)
+
+
+def segment_table(kappa, theta, count, seg_id=None, drift=None):
+    """A segment table as a numpy structured array of SEGMENT_DTYPE (the
+    kappa_segment layout), built from per-segment arrays without a Python loop:
+    the form to use for plans of millions of segments.  seg_id defaults to
+    0, 1, 2, ...; drift (shape (n, 3)) to zero."""
+    import numpy as np
+    kappa = np.asarray(kappa, dtype=np.float64)
+    n = kappa.size
+    t = np.zeros(n, dtype=_segment_dtype())
+    t["kappa"] = kappa
+    t["theta"] = np.broadcast_to(np.asarray(theta, dtype=np.float64), (n,))
+    t["count"] = np.broadcast_to(np.asarray(count, dtype=np.uint64), (n,))
+    t["seg_id"] = np.arange(n, dtype=np.uint32) if seg_id is None else np.asarray(seg_id, dtype=np.uint32)
+    if drift is not None:
+        t["drift"] = np.asarray(drift, dtype=np.float64).reshape(n, 3)
+    return t
+
+
 def _segments(segments):
     """Builds a ctypes array of Segment from Segment objects or dicts/tuples
-    (kappa, theta, (dx, dy, dz), count, seg_id)."""
+    (kappa, theta, (dx, dy, dz), count, seg_id), or views a contiguous numpy
+    array of SEGMENT_DTYPE (segment_table) without copying."""
+    if type(segments).__module__ == "numpy" and getattr(segments, "dtype", None) == _segment_dtype():
+        if not segments.flags["C_CONTIGUOUS"] or not segments.flags["WRITEABLE"]:
+            raise ValueError("a segment table must be a contiguous, writeable numpy array")
+        return (Segment * segments.size).from_buffer(segments)
     arr = (Segment * len(segments))()
     for i, s in enumerate(segments):
         if isinstance(s, Segment):
@@ -289,7 +324,10 @@ def load_particles(segments, cells, seed, precision=FP32, device=None, stream=No
 def sample_batched(segments, seed, precision=FP32, out=None, device=None, stream=None):
     """One-shot batched sampling (kappa_sample_batched, synchronous)."""
     segs = _segments(segments)
-    total = sum(int(s.count) for s in segs)
+    if type(segments).__module__ == "numpy":
+        total = int(segments["count"].sum(dtype="u8"))
+    else:
+        total = sum(int(s.count) for s in segs)
     vx, vy, vz = _outputs(total, precision, out, device)
     st = _lib.load().kappa_sample_batched(segs, len(segs), seed, precision, _ptr(vx), _ptr(vy), _ptr(vz),
                                           _stream(stream, vx.device))

@@ -268,3 +268,25 @@ def test_no_fallback_without_the_library(monkeypatch, tmp_path):
         kp.params(3.0)
     with pytest.raises(RuntimeError, match="no fallback"):
         kp.version()
+
+
+def test_segment_table_layout_and_limit():
+    """SEGMENT_DTYPE has the kappa_segment layout, a numpy table is passed
+    without copying and equals the dict form byte for byte, and a count above
+    KAPPA_MAX_SEGMENTS is refused before the table is read."""
+    d = kp.SEGMENT_DTYPE
+    assert d.itemsize == ctypes.sizeof(_lib.Segment) == 56
+    for name in d.names:
+        assert d.fields[name][1] == getattr(_lib.Segment, name).offset, name
+    t = kp.segment_table([3.0, 4.1, 1.6], [1.0, 0.5, 2.0], [5, 0, 7], seg_id=[9, 3, 4],
+                         drift=[[0.1, 0, 0], [0, 0.2, 0.3], [0, 0, -1]])
+    view = kp._segments(t)
+    ref = kp._segments([(3.0, 1.0, (0.1, 0, 0), 5, 9), (4.1, 0.5, (0, 0.2, 0.3), 0, 3), (1.6, 2.0, (0, 0, -1), 7, 4)])
+    assert bytes(view) == bytes(ref)
+    t["count"][0] = 11  # a view, not a copy
+    assert view[0].count == 11
+    with pytest.raises(ValueError):
+        kp._segments(t[::2])
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.kappa_plan_create(view, (1 << 24) + 1, 0, 1, ctypes.byref(h)) == _lib.ERANGE

@@ -152,3 +152,24 @@ def test_single_segment_plan_equals_sample(c4):
     a = to_host(*kp.sample_batched([seg], 9, kp.FP32))
     b = to_host(*kp.sample(2.5, 1.0, 1_000_003, 9, precision=kp.FP32))
     assert bits_equal(a, b)
+
+
+def test_maximum_segment_count():
+    """KAPPA_MAX_SEGMENTS = 2^24 segments of one particle each, with six kappa
+    values and random theta, from a numpy segment table: sampled segments
+    (both ends and 300 random ones) equal single-species calls bit for bit."""
+    n = 1 << 24
+    rng = np.random.default_rng(24)
+    kappas = np.array([1.6, 2.0, 3.0, 4.1, 7.5, 10.0])
+    table = kp.segment_table(kappas[rng.integers(0, kappas.size, n)], rng.uniform(0.5, 2.0, n), 1)
+    print("segment table built", flush=True)
+    with kp.Plan(table, 6, kp.FP32) as plan:
+        assert plan.total == n
+        out = plan.outputs()
+        plan.launch(out)
+        torch.cuda.synchronize()
+        host = to_host(*out)
+    for s in np.concatenate([[0, 1, n - 2, n - 1], rng.integers(0, n, 300)]):
+        s = int(s)
+        v = kp.sample(table["kappa"][s], table["theta"][s], 1, 6, seg_id=s, precision=kp.FP32)
+        assert bits_equal(tuple(h[s:s + 1] for h in host), to_host(*v)), s
