@@ -160,7 +160,8 @@ typedef struct kappa_plan_s *kappa_plan;
 
 /* kappa_plan_create -- validate segs (host array of nseg, 1 <= nseg <=
  * KAPPA_MAX_SEGMENTS, each with a valid kappa and theta, finite drift,
- * reserved = 0), compute each segment's Table 1 setup in FP64 on the host,
+ * reserved = 0, and seg_id values distinct: segments sharing a seg_id would
+ * draw the same counters, so a repeated seg_id is KAPPA_EINVAL), compute each segment's Table 1 setup in FP64 on the host,
  * lay segments out back to back in the given order (segment s starts at the
  * sum of the earlier counts), and upload the tables.  Allocates device memory
  * (KAPPA_ENOMEM on failure) on the current device; synchronous.  *out owns it
@@ -195,12 +196,12 @@ KAPPA_API kappa_status kappa_plan_shape(kappa_plan plan, int *block, int *unroll
  * grid >= 1; KAPPA_EINVAL otherwise).  Output does not depend on the shape. */
 KAPPA_API kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int grid);
 
-/* Release the plan's device memory and graph.  NULL is a no-op. */
 /* kappa_plan_set_cells -- give the plan one cell box per segment (host array
  * of the plan's nseg cells, in segment order; copied to a plan-owned device
  * table, so the host array may be freed).  NULL removes the table.  Replacing
  * a table synchronises the device.  KAPPA_EINVAL for a non-finite lo or a
- * size that is negative or not finite. */
+ * size that is negative or not finite, and, for a plan of an FP32 precision,
+ * for lo, size or lo + size that overflow float. */
 KAPPA_API kappa_status kappa_plan_set_cells(kappa_plan plan, const kappa_cell *cells);
 
 /* kappa_plan_launch_pic / kappa_plan_graph_launch_pic -- fused particle
@@ -211,7 +212,11 @@ KAPPA_API kappa_status kappa_plan_set_cells(kappa_plan plan, const kappa_cell *c
  * (velocities use draw 0 and are bit-identical to kappa_plan_launch):
  * u = (r + 1/2) 2^-32 in KAPPA_FP64, (floor(r / 2^9) + 1/2) 2^-23 in the
  * FP32 modes, for r = r0, r1, r2 on x, y, z; one fused multiply-add in the
- * output precision.  KAPPA_EINVAL without kappa_plan_set_cells.
+ * output precision, with lo and size rounded to it.  The box is half-open:
+ * lo <= p < lo + size in that precision's values (a fused multiply-add that
+ * rounds up to lo + size is capped at the largest value below it; a box of
+ * size 0 puts every particle at lo).  KAPPA_EINVAL without
+ * kappa_plan_set_cells.
  * Asynchronous. */
 KAPPA_API kappa_status kappa_plan_launch_pic(kappa_plan plan, void *px, void *py, void *pz, void *vx, void *vy,
                                              void *vz, void *stream);

@@ -61,6 +61,8 @@ def _load():
     lib.oracle_sample_indices.restype = None
     lib.oracle_positions.argtypes = [dp, dp, c_u64, c_u64, c_u64, c_u32, c_int, dp, dp, dp]
     lib.oracle_positions.restype = None
+    lib.oracle_position_coord.argtypes = [c_d, c_d, c_u32, c_int]
+    lib.oracle_position_coord.restype = c_d
     lib.oracle_backward.argtypes = [c_d, c_d, c_u64, c_u64, c_u64, c_u32, c_int, fp, fp, fp, dp]
     lib.oracle_backward.restype = None
     lib.oracle_find_tails.argtypes = [c_u64, c_u64, c_u64, c_u32, u64p, c_u64]
@@ -160,6 +162,12 @@ def positions(lo, size, n, seed, counter_offset=0, seg=0, mode=MODE_FP64):
     lib.oracle_positions(_ptr(lo, ctypes.c_double), _ptr(size, ctypes.c_double), n, seed, counter_offset, seg,
                          mode, *(_ptr(a, ctypes.c_double) for a in out))
     return tuple(out)
+
+
+def position_coord(lo, size, r, mode=MODE_FP64):
+    """One coordinate of a position in the box [lo, lo + size) from the
+    Philox word r (what positions() does per axis)."""
+    return float(_load().oracle_position_coord(float(lo), float(size), int(r), mode))
 
 
 def sample_indices(kappa, theta, idx, seed, seg=0, mode=MODE_FP64, drift=None):

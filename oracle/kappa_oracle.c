@@ -341,7 +341,37 @@ uint64_t oracle_sample(double kappa, double theta, const double *drift, uint64_t
  * where u_k is the open midpoint dyadic of word r_k (k = 0, 1, 2):
  * (r_k + 1/2) 2^-32 in FP64 mode and (floor(r_k / 2^9) + 1/2) 2^-23 in the
  * FP32 modes (24 significant bits: exact in float, below 1).  FP64
- * arithmetic. */
+ * arithmetic.
+ *
+ * The box is half-open, [lo, lo + size).  u < 1, but lo + u size rounded to
+ * the nearest double can still reach lo + size when |lo| is large against
+ * size (lo = 1e8, size = 1, u = 1 - 2^-33), so the result is capped at the
+ * largest double strictly below the real number lo + size.  A box of size 0
+ * places every particle at lo. */
+
+/* Largest double strictly below the real lo + size (size > 0), never below
+ * lo: the rounded sum s and its exact rounding error (Knuth's two-sum) tell
+ * whether s lies below the real sum (then s is the answer) or not (then the
+ * double just below s is). */
+static double box_upper(double lo, double size)
+{
+    if (!(size > 0.0)) return lo;
+    const double s = lo + size;
+    const double t = s - lo;
+    const double err = (lo - (s - t)) + (size - t);
+    const double hi = err > 0.0 ? s : nextafter(s, -INFINITY);
+    return hi > lo ? hi : lo;
+}
+
+/* Coordinate of one axis from the Philox word r. */
+double oracle_position_coord(double lo, double size, uint32_t r, int mode)
+{
+    const double u = mode == MODE_FP64 ? ldexp((double)r + 0.5, -32) : ldexp((double)(r >> 9) + 0.5, -23);
+    const double p = lo + u * size;
+    const double hi = box_upper(lo, size);
+    return p < hi ? p : hi;
+}
+
 void oracle_positions(const double *lo, const double *size, uint64_t n, uint64_t seed,
                       uint64_t counter_offset, uint32_t seg, int mode, double *px, double *py,
                       double *pz)
@@ -349,14 +379,10 @@ void oracle_positions(const double *lo, const double *size, uint64_t n, uint64_t
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < (int64_t)n; ++j) {
         uint32_t r[4];
-        double u[3];
         particle_block(seed, counter_offset + (uint64_t)j, seg, 1, r);
-        for (int k = 0; k < 3; ++k)
-            u[k] = mode == MODE_FP64 ? ldexp((double)r[k] + 0.5, -32)
-                                     : ldexp((double)(r[k] >> 9) + 0.5, -23);
-        px[j] = lo[0] + u[0] * size[0];
-        py[j] = lo[1] + u[1] * size[1];
-        pz[j] = lo[2] + u[2] * size[2];
+        px[j] = oracle_position_coord(lo[0], size[0], r[0], mode);
+        py[j] = oracle_position_coord(lo[1], size[1], r[1], mode);
+        pz[j] = oracle_position_coord(lo[2], size[2], r[2], mode);
     }
 }
 

@@ -1,10 +1,12 @@
 // api.hip -- the C ABI of libkappa (declared in include/kappa.h): argument
 // validation, device checks, error mapping and kernel dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "kappa_internal.hpp"
 
@@ -496,6 +498,13 @@ static kappa_status validate_segments(const kappa_segment *segs, uint32_t nseg, 
         total += g.count;
     }
     if (total / 1024 >= UINT32_MAX) return fail(KAPPA_ERANGE, "total particle count too large for the tile map");
+    // Particle j of a segment draws counter (j, seg_id): two segments with one
+    // seg_id would draw the same uniforms.
+    std::vector<uint32_t> ids(nseg);
+    for (uint32_t s = 0; s < nseg; ++s) ids[s] = segs[s].seg_id;
+    std::sort(ids.begin(), ids.end());
+    const auto dup = std::adjacent_find(ids.begin(), ids.end());
+    if (dup != ids.end()) return fail(KAPPA_EINVAL, "seg_id %u appears in more than one segment", *dup);
     return KAPPA_OK;
 }
 

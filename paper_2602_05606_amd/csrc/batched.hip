@@ -18,12 +18,15 @@
 // px, py, pz = lo + u * size with u from the block of draw 1 of the
 // particle's counter (velocities use draw 0, so they are unchanged).
 // u = (r + 1/2) 2^-32 in FP64; in FP32 u = (floor(r / 2^9) + 1/2) 2^-23,
-// exact in float and below 1.
+// exact in float and below 1.  The box is half-open: a rounded lo + u size
+// that reaches lo + size is capped at the largest value of the output type
+// below it (precomputed per cell on the host).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -48,11 +51,11 @@ struct alignas(16) SegF64 {
 };
 
 struct CellF32 {
-    float lo[3], size[3];
+    float lo[3], size[3], hi[3];  // hi: largest float below the real lo + size (lo if size is 0)
 };
 
 struct CellF64 {
-    double lo[3], size[3];
+    double lo[3], size[3], hi[3];
 };
 
 struct BatchArgs {
@@ -127,7 +130,7 @@ struct CellParams {
     __device__ __forceinline__ float coord(int k, uint32_t r) const
     {
         const float u = fmaf(static_cast<float>(r >> 9), 0x1p-23f, 0x1p-24f);
-        return fmaf(u, q.size[k], q.lo[k]);
+        return fminf(fmaf(u, q.size[k], q.lo[k]), q.hi[k]);
     }
 };
 
@@ -138,7 +141,7 @@ struct CellParams<kModeF64> {
     __device__ __forceinline__ double coord(int k, uint32_t r) const
     {
         const double u = fma(static_cast<double>(r), 0x1p-32, 0x1p-33);
-        return fma(u, q.size[k], q.lo[k]);
+        return fmin(fma(u, q.size[k], q.lo[k]), q.hi[k]);
     }
 };
 
@@ -653,6 +656,25 @@ struct PlanDevice {
 }  // namespace
 }  // namespace kappa
 
+namespace kappa {
+namespace {
+// Largest value of T strictly below the real number lo + size, and not below
+// lo (lo itself when size is 0): the rounded sum s and its exact error
+// (Knuth's two-sum, in T's own arithmetic) tell whether s lies below the
+// real sum (then s is the answer) or not (then the value just below s is).
+template <typename T>
+T box_upper(T lo, T size)
+{
+    if (!(size > T(0))) return lo;
+    const T s = lo + size;
+    const T t = s - lo;
+    const T err = (lo - (s - t)) + (size - t);
+    const T hi = err > T(0) ? s : std::nextafter(s, -std::numeric_limits<T>::infinity());
+    return hi > lo ? hi : lo;
+}
+}  // namespace
+}  // namespace kappa
+
 extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell *cells)
 {
     PlanDevice guard(p);
@@ -677,8 +699,14 @@ extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell
         for (int k = 0; k < 3; ++k) {
             c64[s].lo[k] = cells[s].lo[k];
             c64[s].size[k] = cells[s].size[k];
+            c64[s].hi[k] = box_upper(c64[s].lo[k], c64[s].size[k]);
             c32[s].lo[k] = static_cast<float>(cells[s].lo[k]);
             c32[s].size[k] = static_cast<float>(cells[s].size[k]);
+            c32[s].hi[k] = box_upper(c32[s].lo[k], c32[s].size[k]);
+            if (p->mode != kModeF64 &&
+                !(std::isfinite(c32[s].lo[k]) && std::isfinite(c32[s].size[k]) &&
+                  std::isfinite(c32[s].lo[k] + c32[s].size[k])))
+                return fail(KAPPA_EINVAL, "cell %u: lo, size and lo + size must be finite as floats for an FP32 plan", s);
         }
     const size_t o64 = (c32.size() * sizeof(CellF32) + 255) & ~static_cast<size_t>(255);
     const size_t bytes = o64 + c64.size() * sizeof(CellF64);

@@ -134,6 +134,22 @@ def test_plan_argument_checks():
     assert lib.kappa_plan_launch(None, FAKE, FAKE, FAKE, None) == _lib.EINVAL
 
 
+def test_plan_refuses_a_repeated_seg_id():
+    """Particle j of a segment draws counter (j, seg_id): two segments with one
+    seg_id (say the species index reused across cells) would repeat the same
+    velocities, so the table is refused before any device call."""
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    dup = kp._segments([(3.0, 1.0, (0, 0, 0), 10, 7), (2.0, 1.0, (0.1, 0, 0), 5, 3), (3.0, 1.0, (1, 0, 0), 10, 7)])
+    assert lib.kappa_plan_create(dup, 3, 0, 1, ctypes.byref(h)) == _lib.EINVAL
+    assert b"seg_id 7" in lib.kappa_last_error()
+    cells = (kp.Cell * 3)()
+    assert lib.kappa_load_particles(dup, cells, 3, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    t = kp.segment_table([3.0] * 4, [1.0] * 4, [1] * 4, seg_id=[0, 1, 2, 1])
+    assert lib.kappa_plan_create(t.ctypes.data_as(ctypes.POINTER(kp.Segment)), 4, 0, 1,
+                                 ctypes.byref(h)) == _lib.EINVAL
+
+
 def test_exact_and_probe_argument_checks():
     lib = _lib.load()
     assert lib.kappa_sample_exact_t(1.5, 1.0, 10, 0, 1, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL

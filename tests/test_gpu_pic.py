@@ -5,7 +5,8 @@
 * positions match the oracle (oracle.positions) per segment: FP64 to a few
   ulps of |lo| + |size| (one fused multiply-add against the oracle's two
   roundings), FP32 to 2^-22 (|lo| + |size|) (float lo and size, one fmaf);
-* positions lie in their cell's box;
+* positions lie in their cell's half-open box, also for the largest Philox
+  words, whose fused multiply-add rounds up to the box's upper edge;
 * graph replays, the one-shot entry point, ragged and misaligned outputs give
   the same bits; a launch without cells is refused.
 """
@@ -65,8 +66,9 @@ def test_positions_against_oracle_and_velocities_unchanged(orc, c4, prec):
             if prec == kp.FP64:
                 assert np.all(got >= lo[k]) and np.all(got < lo[k] + size[k])
             else:
-                lo32, hi32 = np.float32(lo[k]), np.float32(lo[k] + size[k])
-                assert np.all(got >= lo32) and np.all(got <= hi32)
+                # the FP32 box: lo and size rounded to float, half-open
+                lo32, size32 = np.float64(np.float32(lo[k])), np.float64(np.float32(size[k]))
+                assert np.all(got >= lo32) and np.all(got < lo32 + size32)
     print(f"prec {prec}: worst position error {worst:.2e} of |lo| + |size|")
 
 
@@ -146,3 +148,35 @@ def test_refused_without_cells(c4):
         bad[3, 1, 0] = -1.0
         with pytest.raises(kp.KappaError):
             plan.set_cells(bad)
+
+
+def test_largest_words_stay_below_the_upper_edge(orc):
+    """In FP32 with lo = 3.5 and size = 0.5 the top 2^10 words (u within
+    2^-22 of 1) give fmaf(u, 0.5, 3.5) = 4.0, the next cell's lower corner;
+    the kernel caps them at the largest float below 4.  2^24 particles hold
+    some such words on every axis; all positions are checked against the
+    oracle (which caps in FP64) and against the box."""
+    n, seed, seg = 1 << 24, 21, 5
+    lo, size = np.array([3.5, 3.5, -4.0]), np.array([0.5, 0.5, 0.5])
+    segs = [dict(kappa=3.0, theta=1.0, drift=(0, 0, 0), count=n, seg_id=seg)]
+    with kp.Plan(segs, seed, kp.FP32) as plan:
+        plan.set_cells(np.array([[lo, size]]))
+        pos, vel = plan.outputs(), plan.outputs()
+        plan.launch_pic(pos, vel)
+        words = kp.philox(n, seed, seg_id=seg, draw=1)
+        torch.cuda.synchronize()
+        host = to_host(*pos)
+        words = words.cpu().numpy().view(np.uint32).reshape(n, 4)
+    del pos, vel
+    ref = orc.positions(lo, size, n, seed, seg=seg, mode=1)
+    capped = 0
+    for k in range(3):
+        got = host[k]
+        assert np.all(got >= lo[k]) and np.all(got < lo[k] + size[k])
+        assert np.all(np.abs(got - ref[k]) <= 2.0 ** -22 * (abs(lo[k]) + size[k]))
+        top = np.nonzero(words[:, k] >= 0xFFFFFC00)[0]
+        assert top.size > 0, k
+        edge = np.float32(lo[k] + size[k])
+        assert np.all(got[top] == np.float64(np.nextafter(edge, np.float32(-np.inf)))), k
+        capped += top.size
+    print(f"{capped} coordinates at the cap")

@@ -63,3 +63,35 @@ def test_counter_offset_and_segments(orc):
     for k in range(3):
         np.testing.assert_array_equal(a[k][40:], b[k][:60])
         assert not np.any(a[k] == c[k])
+
+
+@pytest.mark.parametrize("lo, size, mode", [(3.5, 0.5, 1), (1e8, 1.0, 0), (1e8, 1.0, 1), (-4.0, 0.5, 0),
+                                            (-4.0, 0.5, 1), (0.0, 1e-300, 0), (2.0, 1e-17, 0), (5.0, 0.0, 0)])
+def test_extreme_words_stay_inside_the_half_open_box(orc, lo, size, mode):
+    """The largest words give u = 1 - 2^-33 (FP64 mode) or 1 - 2^-24 (FP32
+    modes): lo + u size then rounds to lo + size when |lo| is large against
+    size, and the oracle caps it at the largest double below lo + size.
+    Checked in exact rational arithmetic."""
+    from fractions import Fraction
+    for r in (0, 1, 0x7FFFFFFF, 0xFFFFFE00, 0xFFFFFFFF):
+        p = orc.position_coord(lo, size, r, mode)
+        assert Fraction(p) >= Fraction(lo)
+        if size > 0:
+            assert Fraction(p) < Fraction(lo) + Fraction(size), (lo, size, r, p)
+        else:
+            assert p == lo
+
+
+def test_cap_only_where_rounding_reaches_the_upper_edge(orc):
+    """Away from the edge the coordinate is lo + u size in FP64 (two
+    roundings); at lo = 1e8, size = 1 the top word would round to 1e8 + 1
+    and is capped to the double just below it."""
+    rng = np.random.default_rng(5)
+    for r in rng.integers(0, 2 ** 32 - 1024, size=2000, dtype=np.uint64):
+        u = (float(r) + 0.5) * 2.0 ** -32
+        assert orc.position_coord(-3.0, 0.25, int(r), 0) == -3.0 + u * 0.25
+        u32 = (float(int(r) >> 9) + 0.5) * 2.0 ** -23
+        assert orc.position_coord(100.0, 1e-3, int(r), 1) == 100.0 + u32 * 1e-3
+    u = (float(0xFFFFFFFF) + 0.5) * 2.0 ** -32
+    assert 1e8 + u * 1.0 == 1e8 + 1.0
+    assert orc.position_coord(1e8, 1.0, 0xFFFFFFFF, 0) == np.nextafter(1e8 + 1.0, -np.inf)
