@@ -193,7 +193,8 @@ KAPPA_API kappa_status kappa_plan_autotune(kappa_plan plan, void *vx, void *vy, 
 KAPPA_API kappa_status kappa_plan_shape(kappa_plan plan, int *block, int *unroll, int *grid);
 
 /* Set the launch shape explicitly (block in {64,128,256}, unroll in {1,2,4,8},
- * grid >= 1; KAPPA_EINVAL otherwise).  Output does not depend on the shape. */
+ * 1 <= grid <= 2^23; KAPPA_EINVAL otherwise).  Output does not depend on the
+ * shape. */
 KAPPA_API kappa_status kappa_plan_set_shape(kappa_plan plan, int block, int unroll, int grid);
 
 /* kappa_plan_set_cells -- give the plan one cell box per segment (host array
@@ -380,8 +381,8 @@ KAPPA_API kappa_status kappa_copy_probe(const void *src, void *dst, uint64_t byt
  *               4 * ceil(n / 64) entries always suffice.
  * The outputs must be 16-byte aligned (KAPPA_EALIGN otherwise), the launch
  * shape the default one (KAPPA_EINVAL when KAPPA_FORWARD_SHAPE changes the
- * particles per thread), and n within one launch (2^40 particles in FP32,
- * 2^39 in FP64; KAPPA_ERANGE otherwise).  n = 0 writes *blocks = 0 and launches
+ * particles per thread), and n within one launch (2^33 particles in FP32,
+ * 2^32 in FP64; KAPPA_ERANGE otherwise).  n = 0 writes *blocks = 0 and launches
  * nothing.  Asynchronous like kappa_sample. */
 KAPPA_API kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed,
                                          uint64_t counter_offset, uint32_t seg_id, int precision, void *vx, void *vy,

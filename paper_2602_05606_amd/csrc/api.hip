@@ -266,9 +266,11 @@ size_t kappa_backward_workspace_bytes(uint64_t n)
     return (bytes + 255) & ~static_cast<size_t>(255);
 }
 
-kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
-                                   uint32_t seg_id, int precision, const void *gx, const void *gy, const void *gz,
-                                   double *grad, void *workspace, size_t workspace_bytes, void *stream)
+namespace {
+// Checks shared by the two backward entry points (everything but the
+// partial-sum buffer).
+kappa_status backward_checks(double kappa, double theta, uint64_t n, uint64_t counter_offset, int precision,
+                             const void *gx, const void *gy, const void *gz, const double *grad)
 {
     if (!kappa_ok(kappa)) return fail(KAPPA_EINVAL, "kappa must be finite and > 3/2 (got %g)", kappa);
     if (!theta_ok(theta)) return fail(KAPPA_EINVAL, "theta must be finite and > 0 (got %g)", theta);
@@ -282,13 +284,13 @@ kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint6
     if (n > 0 && (reinterpret_cast<uintptr_t>(gx) % e || reinterpret_cast<uintptr_t>(gy) % e ||
                   reinterpret_cast<uintptr_t>(gz) % e))
         return fail(KAPPA_EALIGN, "gradient pointers must be aligned to %zu bytes", e);
-    if (!workspace) return fail(KAPPA_EINVAL, "null workspace");
-    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(KAPPA_EALIGN, "workspace must be 256-byte aligned");
-    if (workspace_bytes < kappa_backward_workspace_bytes(n))
-        return fail(KAPPA_ERANGE, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes,
-                    kappa_backward_workspace_bytes(n));
-    kappa_status st = require_device();
-    if (st != KAPPA_OK) return st;
+    return KAPPA_OK;
+}
+
+kappa_status backward_launch(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                             uint32_t seg_id, int precision, const void *gx, const void *gy, const void *gz,
+                             double *grad, double *partials, void *stream)
+{
     const Setup s = make_setup(kappa);
     BwdArgs a;
     a.n = n;
@@ -299,10 +301,28 @@ kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint6
     a.gx = gx;
     a.gy = gy;
     a.gz = gz;
-    a.partials = static_cast<double *>(workspace);
+    a.partials = partials;
     a.s64 = species_f64(s, theta);
     a.s32 = species_f32(s, theta);
     return check_hip(launch_backward(precision, a, grad, static_cast<hipStream_t>(stream)), "backward kernel launch");
+}
+}  // namespace
+
+kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
+                                   uint32_t seg_id, int precision, const void *gx, const void *gy, const void *gz,
+                                   double *grad, void *workspace, size_t workspace_bytes, void *stream)
+{
+    kappa_status st = backward_checks(kappa, theta, n, counter_offset, precision, gx, gy, gz, grad);
+    if (st != KAPPA_OK) return st;
+    if (!workspace) return fail(KAPPA_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(KAPPA_EALIGN, "workspace must be 256-byte aligned");
+    if (workspace_bytes < kappa_backward_workspace_bytes(n))
+        return fail(KAPPA_ERANGE, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes,
+                    kappa_backward_workspace_bytes(n));
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    return backward_launch(kappa, theta, n, seed, counter_offset, seg_id, precision, gx, gy, gz, grad,
+                           static_cast<double *>(workspace), stream);
 }
 
 kappa_status kappa_philox(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id, uint32_t draw,
@@ -339,7 +359,7 @@ kappa_status kappa_sample_exact_t(double kappa, double theta, uint64_t n, uint64
     if (st != KAPPA_OK || n == 0) return st;
     st = require_device();
     if (st != KAPPA_OK) return st;
-    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), vx, vy, vz, iters, kappa, theta};
+    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), 0, 0, vx, vy, vz, iters, kappa, theta};
     return check_hip(launch_exact_t(precision, a, static_cast<hipStream_t>(stream)), "exact t kernel launch");
 }
 
@@ -350,7 +370,7 @@ kappa_status kappa_sample_exact_pareto(double kappa, double theta, uint64_t n, u
     if (st != KAPPA_OK || n == 0) return st;
     st = require_device();
     if (st != KAPPA_OK) return st;
-    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), vx, vy, vz, iters, kappa, theta};
+    ExactArgs a{n, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), 0, 0, vx, vy, vz, iters, kappa, theta};
     return check_hip(launch_exact_pareto(precision, a, static_cast<hipStream_t>(stream)), "exact Pareto kernel launch");
 }
 

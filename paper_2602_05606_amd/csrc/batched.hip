@@ -34,6 +34,7 @@
 
 #include "kappa_device.hpp"
 #include "kappa_internal.hpp"
+#include "kappa_store.hpp"
 
 namespace kappa {
 
@@ -86,24 +87,6 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t *start, uint32_t
     return lo;
 }
 
-template <typename T, int U>
-__device__ __forceinline__ void store_group_b(T *p, const T (&v)[U])
-{
-    constexpr int kBytes = U * static_cast<int>(sizeof(T));
-    if constexpr (kBytes % 16 == 0) {
-#pragma unroll
-        for (int c = 0; c < kBytes / 16; ++c) {
-            if constexpr (sizeof(T) == 4)
-                reinterpret_cast<float4 *>(p)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
-            else
-                reinterpret_cast<double2 *>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < U; ++k) p[k] = v[k];
-    }
-}
-
 // A group's U particles usually lie in one segment (C4's segments hold about
 // 420 particles): the segment's bounds, id and setup block are loaded once
 // per group and reloaded only where the group crosses into the next segment.
@@ -144,18 +127,6 @@ struct CellParams<kModeF64> {
         return fmin(fma(u, q.size[k], q.lo[k]), q.hi[k]);
     }
 };
-
-template <typename T, int U>
-__device__ __forceinline__ void store_or_tail(T *p, uint64_t j0, uint64_t total, const T (&v)[U])
-{
-    if (j0 + U <= total) {
-        store_group_b<T, U>(p + j0, v);
-    } else {
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (j0 + k < total) p[j0 + k] = v[k];
-    }
-}
 
 template <int MODE, int U, bool POS>
 __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
@@ -291,7 +262,7 @@ bool shape_valid(const Shape &s)
 {
     const bool b = s.block == 64 || s.block == 128 || s.block == 256;
     const bool u = s.unroll == 1 || s.unroll == 2 || s.unroll == 4 || s.unroll == 8;
-    return b && u && s.grid >= 1;
+    return b && u && s.grid >= 1 && s.grid <= (1 << 23);
 }
 
 // ---- autotune cache: a flat JSON object {"key": "block,unroll,grid", ...} ----
@@ -418,7 +389,7 @@ Shape default_batched_shape(int mode, uint64_t total)
     s.unroll = mode == kModeF64 ? 2 : 4;
     const uint64_t groups = (total + s.unroll - 1) / s.unroll;
     const uint64_t need = (groups + s.block - 1) / s.block;
-    s.grid = static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(need, 1ull << 30)));
+    s.grid = static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(need, 1ull << 23)));
     return s;
 }
 
@@ -756,7 +727,7 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
             for (int w : per_cu) {
                 const uint64_t groups = (p->total + u - 1) / u;
                 const uint64_t need = (groups + b - 1) / b;
-                Shape cand{b, u, w > 0 ? w * cus : static_cast<int>(std::min<uint64_t>(need, 1ull << 30))};
+                Shape cand{b, u, w > 0 ? w * cus : static_cast<int>(std::min<uint64_t>(need, 1ull << 23))};
                 if (w > 0 && static_cast<uint64_t>(cand.grid) >= need) continue;  // same as one pass
                 if (!aligned_for(p->mode, cand, o)) continue;
                 const BatchArgs a = batch_args(p, o);

@@ -10,32 +10,9 @@
 
 #include "kappa_device.hpp"
 #include "kappa_internal.hpp"
+#include "kappa_store.hpp"
 
 namespace kappa {
-
-// Stores U consecutive values of T at p (p aligned to U * sizeof(T) bytes
-// whenever U * sizeof(T) >= 16).
-template <typename T, int U>
-__device__ __forceinline__ void store_group(T *p, const T (&v)[U])
-{
-    constexpr int kBytes = U * static_cast<int>(sizeof(T));
-    if constexpr (kBytes % 16 == 0) {
-        constexpr int kPer = 16 / static_cast<int>(sizeof(T));
-#pragma unroll
-        for (int c = 0; c < U / kPer; ++c) {
-            if constexpr (sizeof(T) == 4) {
-                reinterpret_cast<float4 *>(p)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
-            } else {
-                reinterpret_cast<double2 *>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
-            }
-        }
-    } else if constexpr (kBytes == 8 && sizeof(T) == 4) {
-        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < U; ++k) p[k] = v[k];
-    }
-}
 
 // Philox block of particle counter_offset + j0 + k.  When the launch's counter
 // range stays inside one block of 2^32 (HI_UNIFORM, nearly every launch), the
@@ -187,14 +164,15 @@ hipError_t launch_forward_clock(int mode, const Shape &shape, const FwdArgs &arg
 // One thread per group of particles: consecutive workgroups write
 // consecutive address ranges, which measured faster for streaming stores on
 // gfx950 than a grid capped at a few workgroups per CU striding over the
-// arrays.  A launch holds at most max_grid workgroups (2^30; the environment
+// arrays.  A launch holds at most max_grid workgroups (2^23, so that its
+// work-items fit the dispatch packet's 32-bit grid size; the environment
 // variable KAPPA_FORWARD_MAX_GRID lowers it, for tests): launch_forward splits
 // larger calls into consecutive chunks.  KAPPA_FORWARD_SHAPE="block,unroll"
 // overrides the shape for tuning (block in {64,128,256}, unroll in {1,2,4,8}).
 // Results never depend on either.
 uint64_t forward_max_grid()
 {
-    uint64_t cap = 1ull << 30;
+    uint64_t cap = 1ull << 23;
     if (const char *env = std::getenv("KAPPA_FORWARD_MAX_GRID")) {
         const long long v = std::strtoll(env, nullptr, 10);
         if (v > 0 && v < static_cast<long long>(cap)) cap = static_cast<uint64_t>(v);

@@ -83,6 +83,8 @@ hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStrea
 struct ExactArgs {
     uint64_t n;
     uint32_t k0, k1;
+    uint32_t hi;     // high word of the launch's particle indices when it is the same for all (launcher)
+    uint64_t first;  // particle index of the launch's first output (launcher)
     void *vx, *vy, *vz;
     uint32_t *iters;
     double kappa, theta;

@@ -1,0 +1,48 @@
+// kappa_store.hpp -- the structure-of-arrays store of a thread's group of U
+// consecutive particles: one 16-byte store per output array when the group
+// spans 16 bytes (4 floats or 2 doubles), shared by every generator kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace kappa {
+
+// Stores U consecutive values of T at p (p aligned to U * sizeof(T) bytes
+// whenever U * sizeof(T) >= 16).
+template <typename T, int U>
+__device__ __forceinline__ void store_group(T *p, const T (&v)[U])
+{
+    constexpr int kBytes = U * static_cast<int>(sizeof(T));
+    if constexpr (kBytes % 16 == 0) {
+        constexpr int kPer = 16 / static_cast<int>(sizeof(T));
+#pragma unroll
+        for (int c = 0; c < U / kPer; ++c) {
+            if constexpr (sizeof(T) == 4) {
+                reinterpret_cast<float4 *>(p)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+            } else {
+                reinterpret_cast<double2 *>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+            }
+        }
+    } else if constexpr (kBytes == 8 && sizeof(T) == 4) {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k) p[k] = v[k];
+    }
+}
+
+// The group at element j0 of an array of n: the vector store when the whole
+// group lies inside, one element per store for a ragged last group.
+template <typename T, int U>
+__device__ __forceinline__ void store_or_tail(T *p, uint64_t j0, uint64_t n, const T (&v)[U])
+{
+    if (j0 + U <= n) {
+        store_group<T, U>(p + j0, v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (j0 + k < n) p[j0 + k] = v[k];
+    }
+}
+
+}  // namespace kappa
