@@ -64,11 +64,13 @@ def test_c5_precision_and_tail(orc):
     ks32 = ks_paired(speed(g32), speed(o64))
     ks64 = ks_paired(speed(g64), speed(o64))
     d = np.sqrt(sum((a - b) ** 2 for a, b in zip(g32, o64))) / speed(o64)
+    d64 = np.sqrt(sum((a - b) ** 2 for a, b in zip(g64, o64))) / speed(o64)
     report = {"config": "C5: 1e9 particles, kappa 1.6, theta 1, seed 5, chunks of 2^28; every 100th particle",
               "tail_particles_in_1e9": int(len(tails)), "expected_tail_particles": c["n"] * 2.0 ** -20,
               "fp32_vs_oracle_fp64": e32, "fp64_vs_oracle_fp64": e64,
               "ks_speed_fp32_vs_oracle_fp64": ks32, "ks_speed_fp64_vs_oracle_fp64": ks64,
               "fp32_max_norm_relative_error": float(d.max()), "fp32_mean_norm_relative_error": float(d.mean()),
+              "fp64_max_norm_relative_error": float(d64.max()),
               "command": "KAPPA_REPORT_DIR=<dir> python -m pytest -s tests/test_gpu_c5.py (from the repository root)"}
     print(json.dumps(report, indent=1, default=float))
     if os.environ.get("KAPPA_REPORT_DIR"):
@@ -78,5 +80,6 @@ def test_c5_precision_and_tail(orc):
     assert worst(e64) < 1e-12
     assert worst(e32) < 1e-5
     assert float(d.max()) <= 4e-6
+    assert float(d64.max()) <= 1e-13  # the FP64 subsample element by element
     assert ks64 <= 2e-7 and ks32 < 1e-5
     assert abs(len(tails) - c["n"] * 2.0 ** -20) < 6 * np.sqrt(c["n"] * 2.0 ** -20)
