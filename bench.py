@@ -24,95 +24,131 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 METRIC = "particles/sec (3D velocities) and % HBM-write roofline vs same-GPU exact generator"
-KERNEL_SOURCES = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/forward.hip",
-                  "paper_2602_05606_amd/csrc/kappa_params.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_forward_fp32_c2.json")
-VALU_FILE = os.path.join(ROOT, "profiles", "valu_forward_fp32_c2.json")
-# VALU issue capacity: 256 CUs x 4 SIMDs x 2.4 GHz.  Nominal costs: a wave64
-# full-rate FP32 instruction occupies a SIMD for 2 cycles (the 157.3 TFLOP/s
-# FP32 vector peak), a quarter-rate one 8.  The bench prices the kernel with the
-# costs the issue probe measures instead (v_mad_u64_u32 takes about 4).
+# Per hot-path kernel: the sources it is built from (a committed counter
+# profile is used only while they are unchanged), the rocprofv3 name of its
+# product instantiation, the algorithmic HBM bytes per unit (particle), the
+# direction of that traffic, and the file stem of its profiles under profiles/.
+_FWD = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/forward.hip",
+        "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+_BWD = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/backward.hip",
+        "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+_BAT = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/batched.hip",
+        "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+KERNELS = {
+    "c2-fp32": dict(stem="forward_fp32_c2", match="forward_kernel<1, 4, true, false>", sources=_FWD, unit_bytes=12,
+                    traffic="write", label="forward_kernel<FP32 tail, 4 particles/thread>"),
+    "c2-fp64": dict(stem="forward_fp64_c2", match="forward_kernel<0, 2, true, false>", sources=_FWD, unit_bytes=24,
+                    traffic="write", label="forward_kernel<FP64, 2 particles/thread>"),
+    "c3-fp32": dict(stem="backward_fp32_c3", match="backward_kernel<1, 4, true, true>", sources=_BWD, unit_bytes=12,
+                    traffic="read", label="backward_kernel<FP32 tail, 4 particles/thread>"),
+    "c3-fp64": dict(stem="backward_fp64_c3", match="backward_kernel<0, 2, true, true>", sources=_BWD, unit_bytes=24,
+                    traffic="read", label="backward_kernel<FP64, 2 particles/thread>"),
+    "c4-direct": dict(stem="batched_fp32_c4", match="batched_kernel<1, 4, false>", sources=_BAT, unit_bytes=12,
+                      traffic="write", label="batched_kernel<FP32 tail, 4 particles/thread>"),
+    "c4-pic": dict(stem="batched_pic_fp32_c4", match="batched_kernel<1, 4, true>", sources=_BAT, unit_bytes=24,
+                   traffic="write", label="batched_kernel<FP32 tail, positions, 4 particles/thread>"),
+}
+KERNELS["c4-graph"] = dict(KERNELS["c4-direct"])
+# VALU issue capacity: 256 CUs x 4 SIMDs, 2.4 GHz at most.  Issue floor of one
+# wave64 instruction in SIMD-cycles, from the chip's published vector rates:
+# full-rate 32-bit operations 2 (64 lanes at 32 per cycle: the 157.3 TFLOP/s
+# FP32 vector peak), FP64 arithmetic 4 (78.6 TFLOP/s), v_mad_u64_u32 4 (half
+# rate), single-precision transcendentals 8 (quarter rate).  Priced at these
+# floors an instruction mix cannot exceed the chip's capacity: the fraction is
+# a lower bound on the share of issue time the kernel needs.  The issue probe's
+# measured costs (all a little above the floors) are reported beside it.
 SIMD_COUNT = 256 * 4
 SIMD_CYCLES_PER_S = SIMD_COUNT * 2.4e9
-CYCLES_FULL, CYCLES_QUARTER = 2, 8
+ISSUE_FLOOR = {"full_rate": 2.0, "f64": 4.0, "mad_u64_u32": 4.0, "transcendental_f32": 8.0}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(path="c2-fp32"):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNELS[path]["sources"]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when they are missing or were taken on a different kernel source."""
+def load_profile(kind, path):
+    """A committed profile summary (kind 'valu' or 'traffic') of a path's
+    kernel, or None when it is missing or was taken on other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", f"{kind}_{KERNELS[path]['stem']}.json")) as f:
             t = json.load(f)
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_hash():
+    if t.get("kernel_source_sha") != kernel_source_hash(path):
+        return None
+    return t
+
+
+def measured_traffic(launch_bytes, path="c2-fp32"):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (each
+    counter scaled by what it reads for a plain copy of known size in the same
+    run), or None when they are missing or stale."""
+    t = load_profile("traffic", path)
+    if t is None:
         return None
     return {"write_bytes": t["write_bytes_per_launch"], "fetch_bytes": t["fetch_bytes_per_launch"],
             "algorithmic_bytes": launch_bytes, "calibration": t.get("calibration")}
 
 
 def measure_issue_costs(kp):
-    """SIMD-cycles per wave64 instruction of the classes the forward kernel
-    issues, measured on this chip (kappa_issue_probe: saturated issue, in-kernel
+    """SIMD-cycles per wave64 instruction of the classes the kernels issue,
+    measured on this chip (kappa_issue_probe: saturated issue, in-kernel
     clock, so independent of the clock the chip holds)."""
     return {name: kp.issue_cost(name)["cycles"]
-            for name in ("fma_f32", "transcendental_f32", "mad_u64_u32", "fma_f32_literal")}
+            for name in ("fma_f32", "transcendental_f32", "mad_u64_u32", "fma_f64", "fma_f32_literal")}
 
 
-def alu_roofline(particles_per_s, clock=None, costs=None):
-    """VALU-issue roofline of the dominant kernel from its measured instruction
-    counts (rocprofv3 SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32 and the static
-    v_mad_u64_u32 count), priced with the issue costs measured by the issue
-    probe (`costs`; without them the nominal 2, 8 and 8 SIMD-cycles), or None
-    when the counts were taken on other kernel sources.  Full-rate
-    instructions are priced as v_fma_f32 with three VGPR operands; with the
-    probe's literal-operand v_fma_f32 as well, the range between the two
-    prices is reported too.  The peak is the
-    2.4 GHz one; with `clock` (the core clock measured by the clock probe
-    during the same workload) the fraction of the issue capacity at that
-    clock is added."""
-    try:
-        with open(VALU_FILE) as f:
-            v = json.load(f)
-    except (OSError, ValueError):
+def alu_roofline(units_per_s, clock=None, costs=None, path="c2-fp32", profile=None):
+    """VALU-issue roofline of a path's kernel: its committed rocprofv3
+    instruction counts per unit (SQ_INSTS_VALU and the transcendental and FP64
+    classes; v_mad_u64_u32 from the kernel's ISA) priced at the issue floors,
+    against 1024 SIMDs at 2.4 GHz and, with `clock` (the core clock measured
+    during the same workload), at that clock.  None when the counts are
+    missing or were taken on other kernel sources."""
+    v = profile if profile is not None else load_profile("valu", path)
+    if v is None:
         return None
-    if v.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    c = costs or {"fma_f32": CYCLES_FULL, "transcendental_f32": CYCLES_QUARTER, "mad_u64_u32": CYCLES_QUARTER}
-    trans, mad = v["trans_per_particle"], v["mad_u64_per_particle"]
-    full = v["valu_per_particle"] - trans - mad
-    cycles_per_particle = (c["fma_f32"] * full + c["transcendental_f32"] * trans + c["mad_u64_u32"] * mad) / 64.0
-    achieved = particles_per_s * cycles_per_particle
+    pu = v["per_unit"]
+    trans = pu.get("transcendental_f32", 0.0)
+    f64 = pu.get("f64", 0.0)
+    mad = pu.get("mad_u64_u32", 0.0)
+    full = pu["valu"] - trans - f64 - mad
+    mix = {"full_rate": full, "f64": f64, "mad_u64_u32": mad, "transcendental_f32": trans}
+    cycles = sum(ISSUE_FLOOR[k] * n for k, n in mix.items()) / 64.0
+    achieved = units_per_s * cycles
     out = {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
-           "frac": achieved / SIMD_CYCLES_PER_S, "valu_per_particle": v["valu_per_particle"],
-           "per_particle": {"full_rate": full, "transcendental": trans, "mad_u64_u32": mad},
-           "simd_cycles_per_instruction": c,
-           "costs_from": "kappa_issue_probe on this chip" if costs else "nominal rates",
-           "simd_cycles_per_particle": cycles_per_particle}
-    low = None
-    if "fma_f32_literal" in c:
-        # the full-rate price with a literal operand (no three-VGPR operand reads): the low end
-        low = (c["fma_f32_literal"] * full + c["transcendental_f32"] * trans + c["mad_u64_u32"] * mad) / 64.0
-        out["simd_cycles_per_particle_range"] = [low, cycles_per_particle]
+           "frac": achieved / SIMD_CYCLES_PER_S, "kernel": KERNELS[path]["label"],
+           "valu_per_unit": pu["valu"], "per_unit": mix, "issue_floor_simd_cycles": ISSUE_FLOOR,
+           "simd_cycles_per_unit_at_floor": cycles, "counts_from": f"profiles/valu_{KERNELS[path]['stem']}.json"}
+    if costs:
+        out["measured_issue_costs"] = costs
     if clock:
         at_clock = SIMD_COUNT * clock["core_clock_ghz"] * 1e9
         out.update({"measured_clock": clock, "peak_at_measured_clock": at_clock,
                     "frac_at_measured_clock": achieved / at_clock})
-        if low is not None:
-            out["frac_at_measured_clock_range"] = [particles_per_s * low / at_clock, achieved / at_clock]
     return out
+
+
+def hbm_roofline(path, units, ms, clock=None, costs=None):
+    """HBM roofline object of one launch of a path's kernel (algorithmic bytes
+    over the event-timed launch duration against 8 TB/s), with its measured
+    traffic and its VALU-issue fraction where committed counters cover it."""
+    k = KERNELS[path]
+    launch_bytes = k["unit_bytes"] * units
+    achieved = launch_bytes / (ms * 1e-3) / 1e9
+    alu = alu_roofline(units / (ms * 1e-3), clock, costs, path)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(launch_bytes, path), "direction": k["traffic"], "kernel": k["label"],
+            "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": ms,
+            "valu_issue_frac": alu["frac_at_measured_clock" if clock else "frac"] if alu else None}
 
 
 def launch_clock_probe(kp, torch, kappas, theta, n, seed, out):
@@ -146,6 +182,21 @@ def finish_clock_probe(probe, torch, avg_kernel_ms):
             "probe_launch_ms": e0.elapsed_time(e1) / len(runs), "timed_launch_ms": avg_kernel_ms,
             "how": "kappa_clock_probe: the forward kernel with core-clock (s_memtime) and constant-rate "
                    "(s_memrealtime) stamps per workgroup, one launch per kappa after the timed steps"}
+
+
+def step_protocol(step_ms, particles_per_step):
+    """Per-step times of the timed region (HIP events between steps): their
+    median, and the paper's protocol of four runs with the mean of the last
+    three (Sec. 5) taken on the first four timed steps."""
+    srt = sorted(step_ms)
+    med = 0.5 * (srt[(len(srt) - 1) // 2] + srt[len(srt) // 2])
+    out = {"steps": len(step_ms), "step_ms_median": med, "step_ms_min": srt[0], "step_ms_max": srt[-1],
+           "particles_per_s_at_median": particles_per_step / (med * 1e-3)}
+    if len(step_ms) >= 4:
+        paper = sum(step_ms[1:4]) / 3.0
+        out.update({"paper_protocol_step_ms": paper, "paper_protocol_particles_per_s": particles_per_step / (paper * 1e-3),
+                    "paper_protocol": "four runs (the first four timed steps), mean of the last three"})
+    return out
 
 
 def time_launches(fn, reps, torch, warm=2):
@@ -365,30 +416,296 @@ def divergence_survey(kp, torch, dev):
             if np.any(copt == cs[-1]) else None}
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The oracle (FP64 arithmetic at the FP32 mode's uniforms, OpenMP over
-    particles) timed on the host over a bounded sample of the C2 workload."""
-    import numpy as np  # noqa: F401
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def timing_protocol(fn, reps=10):
+    """Runs fn() reps times (reps >= 10) and returns (median s, the paper's
+    protocol of four runs with the mean of the last three (Sec. 5), all
+    times).  The first four runs serve the paper's protocol."""
+    times = []
+    for _ in range(max(reps, 10)):
+        t0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t0)
+    srt = sorted(times)
+    median = 0.5 * (srt[(len(srt) - 1) // 2] + srt[len(srt) // 2])
+    return median, sum(times[1:4]) / 3.0, times
+
+
+def cpu_baseline():
+    """The oracle (plain C, FP64, OpenMP over particles, not tuned) timed on
+    the host, single-threaded and on every core: C1 (1e6 particles, kappa 3,
+    FP64, seed 0) in full, and C2 at kappa 3 in FP64 (seed 1) on a bounded
+    sample of its 1e8 particles (the first 2e7 on all cores, the first 2e6 on
+    one).  Each figure is the median of 10 runs, with the paper's four runs,
+    mean of the last three, beside it.  `value` is the all-core C2 rate."""
     sys.path.insert(0, ROOT)
     import oracle
     import workloads
-    c = workloads.C2
-    probe_n = 200_000
-    t0 = time.perf_counter()
-    oracle.sample(c["kappas"][0], c["theta"], probe_n, c["seed"], mode=oracle.MODE_FP32)
-    rate = probe_n / max(time.perf_counter() - t0, 1e-6)
-    per_kappa = int(min(c["n"], max(1e5, rate * seconds_target / len(c["kappas"]))))
-    t0 = time.perf_counter()
-    for k in c["kappas"]:
-        oracle.sample(k, c["theta"], per_kappa, c["seed"], mode=oracle.MODE_FP32)
-    dt = time.perf_counter() - t0
-    return {"value": per_kappa * len(c["kappas"]) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {per_kappa} particles of each of the 6 C2 kappa values (FP32-mode uniforms, "
-                      f"FP64 arithmetic), {dt:.1f} s on the host"}
+    c1, c2 = workloads.C1, workloads.C2
+    all_cores = oracle.num_threads()
+    res = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "omp_threads_all": all_cores}
+    runs = {}
+    for threads in (all_cores, 1):
+        oracle.set_num_threads(threads)
+        tag = "all_cores" if threads == all_cores else "single_thread"
+        n1 = c1["n"]
+        med, paper, _ = timing_protocol(lambda: oracle.sample(c1["kappa"], c1["theta"], n1, c1["seed"],
+                                                               mode=oracle.MODE_FP64))
+        runs[f"c1_{tag}"] = {"particles": n1, "median_s": med, "paper_mean_of_last_3_of_4_s": paper,
+                             "particles_per_s": n1 / med, "threads": threads}
+        n2 = 20_000_000 if threads == all_cores else 2_000_000
+        med, paper, _ = timing_protocol(lambda: oracle.sample(3.0, c2["theta"], n2, c2["seed"], mode=oracle.MODE_FP64))
+        runs[f"c2_kappa3_{tag}"] = {"particles": n2, "median_s": med, "paper_mean_of_last_3_of_4_s": paper,
+                                    "particles_per_s": n2 / med, "threads": threads}
+        log(f"cpu baseline {tag}: C1 {runs[f'c1_{tag}']['particles_per_s']:.3e}/s, "
+            f"C2 kappa 3 {runs[f'c2_kappa3_{tag}']['particles_per_s']:.3e}/s")
+    oracle.set_num_threads(all_cores)
+    res["runs"] = runs
+    main = runs["c2_kappa3_all_cores"]
+    res.update({"value": main["particles_per_s"], "unit": "particles/s", "cores": all_cores, "kind": "oracle",
+                "sample": f"C2 at kappa 3 in FP64: the first {main['particles']} of its 1e8 particles on "
+                          f"{all_cores} threads, median of 10 runs (single-thread and C1 figures in runs)"})
+    return res
 
 
 EXTRAS = ("rates", "simt", "ks", "test2", "survey", "c5", "fp64", "backward", "batched")
+
+# Single paths for profiling runs (--profile-path): each runs only its own
+# launches, W untimed then K timed, so a rocprofv3 trace or counter pass of the
+# command sees that kernel alone (plus torch's own buffer set-up).
+PROFILE_PATHS = ("c1-fp64", "c2-fp32", "c2-fp64", "c3-fp32", "c3-fp64", "c4-direct", "c4-graph", "c4-caller-graph",
+                 "c4-pic", "copy", "store-fp32", "store-fp64", "exact-t", "exact-pareto")
+
+
+def _rocprof_rows(directory, suffix):
+    """Rows of every rocprofv3 CSV under directory whose name ends in suffix."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(directory):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(root, f), newline="") as fh:
+                    rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _path_units(path):
+    sys.path.insert(0, ROOT)
+    import workloads
+    if path.startswith("c2"):
+        return workloads.C2["n"]
+    if path.startswith("c3"):
+        return workloads.C3["n"]
+    if path.startswith("c4"):
+        return int(sum(s["count"] for s in workloads.batched_segments()))
+    raise SystemExit(f"no unit count for {path}")
+
+
+def summarise_counters(directory, path, command, mad_per_unit=None, note=None):
+    """Reduces a rocprofv3 --pmc run of `bench.py --profile-path <path>` to the
+    per-dispatch means of every counter for the path's kernel and, per unit
+    (particle): wave instructions x 64 / units of the VALU classes, or HBM bytes
+    per launch from FETCH_SIZE / WRITE_SIZE (KiB) scaled by what the same
+    counter reads for the plain copy kernel of 1.2e9 bytes each way in the same
+    run (--calibrate)."""
+    k = KERNELS[path]
+    rows = _rocprof_rows(directory, "counter_collection.csv")
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {directory}")
+    sums = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        who = "kernel" if k["match"] in name else "copy" if "copy_kernel" in name else None
+        if who is None:
+            continue
+        key = (who, r["Counter_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        sums[key] = sums.get(key, 0.0) + float(r["Counter_Value"])
+    per = {}
+    for (who, cname, _), v in sums.items():
+        per.setdefault((who, cname), []).append(v)
+    mean = {key: sum(v) / len(v) for key, v in per.items()}
+    units = _path_units(path)
+    counters = {c: m for (who, c), m in mean.items() if who == "kernel"}
+    if not counters:
+        raise SystemExit(f"no dispatch of {k['match']} in {directory}")
+    out = {"kernel": k["label"], "profile_path": path, "units_per_launch": units,
+           "kernel_source_sha": kernel_source_hash(path),
+           "dispatches": max(len(v) for (who, _), v in per.items() if who == "kernel"),
+           "counters_per_dispatch": counters, "command": command}
+    if "FETCH_SIZE" in counters or "WRITE_SIZE" in counters:
+        copy_bytes = 1.2e9
+        cal = {}
+        for c, field in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+            if c in counters:
+                ratio = mean[("copy", c)] * 1024.0 / copy_bytes if ("copy", c) in mean else None
+                cal[f"{field}_counter_over_true"] = ratio
+                out[f"{field}_kib_raw"] = counters[c]
+                out[f"{field}_bytes_per_launch"] = counters[c] * 1024.0 / ratio if ratio else None
+        cal["copy_bytes_per_launch"] = copy_bytes
+        out["calibration"] = cal
+        out["algorithmic_bytes_per_launch"] = k["unit_bytes"] * units
+        out["algorithmic_direction"] = k["traffic"]
+    else:
+        pu = {"valu": counters["SQ_INSTS_VALU"] * 64.0 / units}
+        if "SQ_INSTS_VALU_TRANS_F32" in counters:
+            pu["transcendental_f32"] = counters["SQ_INSTS_VALU_TRANS_F32"] * 64.0 / units
+        f64 = [c for c in counters if c.startswith("SQ_INSTS_VALU_") and c.endswith("_F64")]
+        if f64:
+            pu["f64"] = sum(counters[c] for c in f64) * 64.0 / units
+            pu["f64_counters"] = f64
+        if mad_per_unit is not None:
+            pu["mad_u64_u32"] = float(mad_per_unit)
+        out["per_unit"] = pu
+    if note:
+        out["notes"] = note
+    return out
+
+
+def summarise_trace(directory, path, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --runtime-trace run of
+    `bench.py --profile-path <path>`: the kernel's durations, the idle gaps
+    between consecutive dispatches, and the host time of the HIP launch calls."""
+    k = KERNELS.get(path, {"match": ""})
+    rows = [r for r in _rocprof_rows(directory, "kernel_trace.csv") if k["match"] in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    st = [int(r["Start_Timestamp"]) for r in rows]
+    en = [int(r["End_Timestamp"]) for r in rows]
+    dur = sorted(e - b for b, e in zip(st, en))
+    gaps = sorted(st[i + 1] - en[i] for i in range(len(rows) - 1))
+    med = lambda v: v[len(v) // 2] if v else float("nan")  # noqa: E731
+    mean = lambda v: sum(v) / len(v) if v else float("nan")  # noqa: E731
+    period = (st[-1] - st[0]) / (len(st) - 1) if len(st) > 1 else float("nan")
+    api = {r["Name"]: r for r in _rocprof_rows(directory, "hip_api_stats.csv")}
+    lines = [f"# Kernel trace of `bench.py --profile-path {path}` on MI355X", "",
+             "Command (from the repository root on the GPU box):", "", f"    {command}", "",
+             f"Kernel `{rows[0]['Kernel_Name'] if rows else k['match']}`: {len(rows)} dispatches "
+             "(warm-up included).  Times in microseconds.", "",
+             "| Quantity | Median | Mean | Min | Max |", "|---|---|---|---|---|",
+             f"| kernel duration | {med(dur) / 1e3:.2f} | {mean(dur) / 1e3:.2f} | {dur[0] / 1e3:.2f} | {dur[-1] / 1e3:.2f} |"
+             if dur else "| kernel duration | - | - | - | - |",
+             f"| idle gap to the next dispatch | {med(gaps) / 1e3:.2f} | {mean(gaps) / 1e3:.2f} | {gaps[0] / 1e3:.2f} | "
+             f"{gaps[-1] / 1e3:.2f} |" if gaps else "| idle gap | - | - | - | - |",
+             f"| dispatch period (start to start) | | {period / 1e3:.2f} | | |", ""]
+    calls = [n for n in ("hipGraphLaunch", "hipLaunchKernel", "hipModuleLaunchKernel", "hipExtLaunchKernel") if n in api]
+    if calls:
+        lines += ["Host time of the launch calls (hip_api_stats.csv):", "", "| Call | Calls | Average us |", "|---|---|---|"]
+        lines += [f"| {n} | {api[n]['Calls']} | {float(api[n]['AverageNs']) / 1e3:.2f} |" for n in calls]
+        lines.append("")
+    return "\n".join(lines)
+
+
+def profile_path(name, steps, warmup, calibrate=False):
+    """Runs one path of the hot path `warmup` times untimed and `steps` times
+    timed with HIP events on the launching stream; prints one JSON line with
+    the average per launch."""
+    import torch
+    sys.path.insert(0, ROOT)
+    import paper_2602_05606_amd as kp
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    c2 = workloads.C2
+    launches, fn, units, unit_bytes = 1, None, 0, 0
+    keep = []
+    if name in ("c1-fp64",):
+        c1 = workloads.C1
+        out = kp.sample(c1["kappa"], c1["theta"], c1["n"], c1["seed"], precision=kp.FP64)
+        fn = lambda: kp.sample(c1["kappa"], c1["theta"], c1["n"], c1["seed"], precision=kp.FP64, out=out)
+        units, unit_bytes = c1["n"], 24
+    elif name in ("c2-fp32", "c2-fp64", "store-fp32", "store-fp64", "exact-t", "exact-pareto"):
+        prec = kp.FP64 if name.endswith("fp64") else kp.FP32
+        out = tuple(torch.empty(c2["n"], dtype=torch.float64 if prec == kp.FP64 else torch.float32, device=dev)
+                    for _ in range(3))
+        launches = len(c2["kappas"])
+        if name.startswith("store"):
+            fn = lambda: [kp.fill_probe(c2["n"], prec, out) for _ in c2["kappas"]]
+        elif name == "exact-t":
+            fn = lambda: [kp.sample_exact_t(k, c2["theta"], c2["n"], c2["seed"], precision=prec, out=out)
+                          for k in c2["kappas"]]
+        elif name == "exact-pareto":
+            fn = lambda: [kp.sample_exact_pareto(k, c2["theta"], c2["n"], c2["seed"], precision=prec, out=out)
+                          for k in c2["kappas"]]
+        else:
+            fn = lambda: [kp.sample(k, c2["theta"], c2["n"], c2["seed"], precision=prec, out=out)
+                          for k in c2["kappas"]]
+        units, unit_bytes = c2["n"], 24 if prec == kp.FP64 else 12
+    elif name in ("c3-fp32", "c3-fp64"):
+        c3 = workloads.C3
+        prec = kp.FP64 if name.endswith("fp64") else kp.FP32
+        gen = torch.Generator(device=dev).manual_seed(c3["grad_seed"])
+        g = torch.randn((3, c3["n"]), generator=gen, device=dev,
+                        dtype=torch.float64 if prec == kp.FP64 else torch.float32)
+        ws = torch.empty(kp.backward_workspace_bytes(c3["n"]), dtype=torch.uint8, device=dev)
+        grad = torch.empty(2, dtype=torch.float64, device=dev)
+        fn = lambda: kp.sample_backward(c3["kappa"], c3["theta"], c3["n"], c3["seed"], g[0], g[1], g[2],
+                                        precision=prec, workspace=ws, out=grad)
+        units, unit_bytes = c3["n"], 24 if prec == kp.FP64 else 12
+    elif name.startswith("c4"):
+        plan = kp.Plan(workloads.batched_segments(), workloads.C4["seed"], kp.FP32)
+        keep.append(plan)
+        outb = plan.outputs()
+        units, unit_bytes = plan.total, 12
+        if name == "c4-direct":
+            fn = lambda: plan.launch(outb)
+        elif name == "c4-graph":
+            plan.graph_launch(outb)
+            fn = lambda: plan.graph_launch(outb)
+        elif name == "c4-pic":
+            plan.set_cells(workloads.batched_cells())
+            posb = plan.outputs()
+            fn = lambda: plan.launch_pic(posb, outb)
+            unit_bytes = 24
+        else:  # c4-caller-graph: 8 plan launches captured into one graph of the caller's
+            bufs = [plan.outputs() for _ in range(8)]
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for b in bufs:
+                    plan.launch(b)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg):
+                for b in bufs:
+                    plan.launch(b)
+            keep.append((bufs, cg))
+            fn, launches = cg.replay, len(bufs)
+    elif name == "copy":
+        src = torch.empty(300_000_000, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        fn = lambda: kp.copy_probe(src, dst)
+        units, unit_bytes = 1, 2 * src.numel() * 4
+    else:
+        raise SystemExit(f"unknown profile path {name}; choose from {', '.join(PROFILE_PATHS)}")
+    log(f"profile path {name}: {warmup} untimed, {steps} timed calls of {launches} launch(es)")
+    ms = time_launches(fn, steps, torch, warm=warmup) / launches
+    if calibrate:
+        # plain copies of 1.2e9 bytes each way: the scale of the traffic counters
+        src = torch.empty(300_000_000, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            kp.copy_probe(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
+    rec = {"profile_path": name, "calls": steps, "warmup": warmup, "launches_per_call": launches,
+           "avg_launch_ms": ms, "units_per_launch": units, "algorithmic_bytes_per_launch": units * unit_bytes,
+           "GB_per_s": units * unit_bytes / (ms * 1e-3) / 1e9}
+    print(json.dumps(rec), flush=True)
+    for k in keep:
+        if isinstance(k, kp.Plan):
+            k.close()
 
 
 def main():
@@ -405,7 +722,31 @@ def main():
     ap.add_argument("--calibrate", action="store_true",
                     help="also run the plain copy probe on 1.2e9 bytes (3 launches) and the store probe, so that "
                          "rocprofv3 counters can be scaled against known traffic")
+    ap.add_argument("--profile-path", choices=PROFILE_PATHS,
+                    help="run only this path's launches (--warmup untimed, --steps timed) for a profiler, print its "
+                         "average launch time and exit")
+    ap.add_argument("--summarise", metavar="DIR",
+                    help="reduce the rocprofv3 output under DIR of a --profile-path run (counters or kernel trace) "
+                         "to the summary committed under profiles/, print it and exit (no GPU)")
+    ap.add_argument("--command", default="", help="with --summarise: the command that produced DIR, recorded")
+    ap.add_argument("--mad-per-unit", type=float, default=None,
+                    help="with --summarise of a VALU pass: v_mad_u64_u32 per particle from the kernel's ISA")
+    ap.add_argument("--note", default=None, help="with --summarise: a note recorded with the summary")
     args = ap.parse_args()
+    if args.summarise:
+        if not args.profile_path:
+            ap.error("--summarise needs --profile-path")
+        if _rocprof_rows(args.summarise, "counter_collection.csv"):
+            print(json.dumps(summarise_counters(args.summarise, args.profile_path, args.command, args.mad_per_unit,
+                                                args.note), indent=1))
+        else:
+            print(summarise_trace(args.summarise, args.profile_path, args.command))
+        return
+    if args.profile_path:
+        if args.gpus != 1:
+            ap.error("profile paths run on one GPU")
+        profile_path(args.profile_path, args.steps, args.warmup, args.calibrate)
+        return
     chosen = set(EXTRAS) if args.extras == "all" else set() if args.extras == "none" else set(args.extras.split(","))
     if args.no_extras:
         chosen = set()
@@ -444,14 +785,20 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done; timing {args.steps} steps")
     events = ([], [])
+    step_ev = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        step_ev.append(torch.cuda.Event(enable_timing=True))
+        step_ev[-1].record()
         step(events=events)
+    step_ev.append(torch.cuda.Event(enable_timing=True))
+    step_ev[-1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernel_ms = [s.elapsed_time(e) for s, e in zip(*events)]
     avg_kernel_ms = sum(kernel_ms) / len(kernel_ms)
+    step_ms = [a.elapsed_time(b) for a, b in zip(step_ev[:-1], step_ev[1:])]
     particles = args.steps * len(kappas) * n
     value = particles / elapsed
     launch_bytes = 12 * n
@@ -468,8 +815,9 @@ def main():
                    "particles_per_step": len(kappas) * n, "kappas": list(kappas), "precision": "FP32+FP64tail"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
-                     "kernel": "forward_kernel<FP32 tail, 4 particles/thread>",
+                     "kernel": KERNELS["c2-fp32"]["label"],
                      "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
+        "timing": step_protocol(step_ms, len(kappas) * n),
     }
     probe = launch_clock_probe(kp, torch, kappas, theta, n, seed, out32)
     result["roofline_alu"] = None  # filled in after the extras, when the stamps are read back
@@ -487,6 +835,7 @@ def main():
             "fill_kernel: 1.2e9 bytes written per launch)")
 
     extras = {}
+    path_ms = {}  # path -> (units per launch, average launch ms), for the roofline objects
     if "rates" in chosen:
         per_kappa = {}
         for k in kappas:
@@ -547,6 +896,7 @@ def main():
             ms = time_launches(lambda: kp.sample(k, theta, n, seed, precision=kp.FP64, out=out64), 10, torch, warm=5)
             fp64[str(k)] = {"particles_per_s": n / (ms * 1e-3), "GB_per_s": 24 * n / (ms * 1e-3) / 1e9}
         extras["fp64_per_kappa"] = fp64
+        path_ms["c2-fp64"] = (n, n / (sum(v["particles_per_s"] for v in fp64.values()) / len(fp64)) * 1e3)
         fill64 = time_launches(lambda: kp.fill_probe(n, kp.FP64, out64), 3, torch)
         extras["store_probe_fp64_GB_per_s"] = 24 * n / (fill64 * 1e-3) / 1e9
         del out64
@@ -560,6 +910,7 @@ def main():
                                                          g[2], precision=kp.FP32, workspace=ws), 20, torch)
         extras["backward_c3"] = {"particles_per_s": c3["n"] / (bw_ms * 1e-3), "ms": bw_ms,
                                  "GB_per_s_read": 12 * c3["n"] / (bw_ms * 1e-3) / 1e9}
+        path_ms["c3-fp32"] = (c3["n"], bw_ms)
         # the same backward in FP64 (FP64 upstream gradient, FP64 inversion throughout)
         g64 = g.double()
         del g
@@ -567,6 +918,7 @@ def main():
                                                            g64[1], g64[2], precision=kp.FP64, workspace=ws), 10, torch)
         extras["backward_c3"]["fp64"] = {"particles_per_s": c3["n"] / (bw64_ms * 1e-3), "ms": bw64_ms,
                                          "GB_per_s_read": 24 * c3["n"] / (bw64_ms * 1e-3) / 1e9}
+        path_ms["c3-fp64"] = (c3["n"], bw64_ms)
         del g64
         log("backward done")
     if "batched" in chosen:
@@ -623,6 +975,9 @@ def main():
                                         "direct_launch_ms": pic_ms, "graph_launch_ms": pic_graph_ms,
                                         "particles_per_s": plan.total / (pic_ms * 1e-3),
                                         "GB_per_s_written": 24 * plan.total / (pic_ms * 1e-3) / 1e9}}
+            path_ms["c4-direct"] = (plan.total, direct_ms)
+            path_ms["c4-graph"] = (plan.total, graph_ms)
+            path_ms["c4-pic"] = (plan.total, pic_ms)
         log("batched done")
     if extras:
         result["extras"] = extras
@@ -632,6 +987,9 @@ def main():
     costs = measure_issue_costs(kp)
     log("issue costs (SIMD-cycles per wave64 instruction): " + ", ".join(f"{k} {v:.2f}" for k, v in costs.items()))
     result["roofline_alu"] = alu_roofline(n / (avg_kernel_ms * 1e-3), clock, costs)
+    # the other paths' kernels: HBM fraction of their timed launches, VALU-issue
+    # fraction at 2.4 GHz (the core clock above was measured on C2 FP32 only)
+    result["rooflines"] = {p: hbm_roofline(p, u, ms, None, costs) for p, (u, ms) in path_ms.items()}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
         log("cpu baseline done")

@@ -42,15 +42,32 @@ def _dtype(precision):
     return torch.float64 if precision == FP64 else torch.float32
 
 
-def _stream(stream, device):
+def _raw_current_stream():
+    """torch's raw current-stream query (no Stream object per call), or None."""
     torch = _torch()
-    if stream is None:
-        stream = torch.cuda.current_stream(device)
-    return ctypes.c_void_p(stream.cuda_stream)
+    return getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+_RAW_STREAM = None
+
+
+def _stream(stream, device):
+    """The HIP stream handle for a call: `stream`'s, or torch's current stream
+    on `device` (a torch.device or a tensor's device)."""
+    global _RAW_STREAM
+    if stream is not None:
+        return stream.cuda_stream
+    if _RAW_STREAM is None:
+        _RAW_STREAM = _raw_current_stream() or False
+    torch = _torch()
+    if _RAW_STREAM:
+        index = device.index if isinstance(device, torch.device) else device
+        return _RAW_STREAM(torch.cuda.current_device() if index is None else index)
+    return torch.cuda.current_stream(device).cuda_stream
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    return t.data_ptr() if t is not None else None
 
 
 def params(kappa):
@@ -89,9 +106,10 @@ def backward_workspace_bytes(n):
 
 
 def sample_backward(kappa, theta, n, seed, gx, gy, gz, *, counter_offset=0, seg_id=0, precision=FP32,
-                    workspace=None, stream=None):
+                    workspace=None, out=None, stream=None):
     """(dLoss/dkappa, dLoss/dtheta) through sample() at fixed uniforms, as a
-    float64 device tensor of 2 elements.  gx, gy, gz: upstream gradients."""
+    float64 device tensor of 2 elements (written into `out` when given).
+    gx, gy, gz: upstream gradients."""
     torch = _torch()
     dev = gx.device
     dt = _dtype(precision)
@@ -102,7 +120,9 @@ def sample_backward(kappa, theta, n, seed, gx, gy, gz, *, counter_offset=0, seg_
     wbytes = backward_workspace_bytes(n)
     if workspace is None:
         workspace = torch.empty(wbytes, dtype=torch.uint8, device=dev)
-    grad = torch.empty(2, dtype=torch.float64, device=dev)
+    grad = torch.empty(2, dtype=torch.float64, device=dev) if out is None else out
+    if grad.dtype != torch.float64 or grad.numel() < 2 or not grad.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of at least 2 elements")
     st = _lib.load().kappa_sample_backward(float(kappa), float(theta), n, seed, counter_offset, seg_id, precision,
                                            _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(grad), _ptr(workspace),
                                            workspace.numel() * workspace.element_size(), _stream(stream, dev))

@@ -306,3 +306,4 @@ def test_segment_table_layout_and_limit():
     lib = _lib.load()
     h = ctypes.c_void_p()
     assert lib.kappa_plan_create(view, (1 << 24) + 1, 0, 1, ctypes.byref(h)) == _lib.ERANGE
+

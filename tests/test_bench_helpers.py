@@ -24,22 +24,75 @@ def test_sup_G_minus_F_against_the_oracle(orc, kappa):
     assert ref * (1 - 1e-9) <= got <= ref * 1.01
 
 
-def test_alu_roofline_prices_and_range():
-    """The VALU-issue roofline: instruction counts of the committed counter run
-    priced per class; the literal-operand FMA price gives the low end of the
-    range, the three-VGPR price the reported figure."""
-    costs = {"fma_f32": 2.4, "transcendental_f32": 8.4, "mad_u64_u32": 4.6, "fma_f32_literal": 2.1}
-    r = bench.alu_roofline(3.5e11, {"core_clock_ghz": 2.0}, costs)
-    assert r is not None, "the committed VALU counts were taken on other kernel sources"
-    pp = r["per_particle"]
-    want = (2.4 * pp["full_rate"] + 8.4 * pp["transcendental"] + 4.6 * pp["mad_u64_u32"]) / 64
-    assert abs(r["simd_cycles_per_particle"] - want) < 1e-12
-    lo, hi = r["simd_cycles_per_particle_range"]
-    assert lo < hi == r["simd_cycles_per_particle"]
-    f_lo, f_hi = r["frac_at_measured_clock_range"]
-    assert f_hi == r["frac_at_measured_clock"] and f_lo < f_hi
-    assert abs(f_hi - 3.5e11 * want / (1024 * 2.0e9)) < 1e-12
+def test_alu_roofline_prices_at_the_issue_floors():
+    """The VALU-issue roofline prices each instruction class at its issue
+    floor (full rate 2, FP64 and v_mad_u64_u32 4, FP32 transcendentals 8
+    SIMD-cycles per wave64 instruction), so a kernel issuing at the chip's
+    capacity reaches exactly 1."""
+    prof = {"per_unit": {"valu": 115.0, "transcendental_f32": 9.0, "mad_u64_u32": 17.25}}
+    r = bench.alu_roofline(3.5e11, {"core_clock_ghz": 2.0}, None, profile=prof)
+    full = 115.0 - 9.0 - 17.25
+    want = (2 * full + 8 * 9.0 + 4 * 17.25) / 64
+    assert abs(r["simd_cycles_per_unit_at_floor"] - want) < 1e-12
     assert abs(r["frac"] - 3.5e11 * want / bench.SIMD_CYCLES_PER_S) < 1e-12
+    assert abs(r["frac_at_measured_clock"] - 3.5e11 * want / (1024 * 2.0e9)) < 1e-12
+    # the rate at which the mix fills every SIMD's issue slots gives 1
+    full_rate = 1024 * 2.0e9 / want
+    assert abs(bench.alu_roofline(full_rate, {"core_clock_ghz": 2.0}, None, profile=prof)["frac_at_measured_clock"]
+               - 1.0) < 1e-12
+    # an FP64 mix
+    prof64 = {"per_unit": {"valu": 300.0, "f64": 150.0, "mad_u64_u32": 17.25}}
+    r64 = bench.alu_roofline(1e11, None, None, profile=prof64)
+    assert abs(r64["simd_cycles_per_unit_at_floor"] - (2 * (300 - 150 - 17.25) + 4 * 150 + 4 * 17.25) / 64) < 1e-12
+
+
+def test_summarise_counters_and_trace(tmp_path):
+    """The reductions of rocprofv3 CSVs behind the committed profiles: per
+    unit instruction counts, traffic scaled by the copy kernel's reading, and
+    the kernel trace's durations and gaps."""
+    import csv
+    d = tmp_path / "pmc" / "host" / "1"
+    d.mkdir(parents=True)
+    units = 10 ** 8
+    rows = []
+    for disp in range(3):
+        rows.append({"Dispatch_Id": disp, "Kernel_Name": "void kappa::forward_kernel<1, 4, true, false>(...)",
+                     "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 110.0 * units / 64})
+        rows.append({"Dispatch_Id": disp, "Kernel_Name": "void kappa::forward_kernel<1, 4, true, false>(...)",
+                     "Counter_Name": "SQ_INSTS_VALU_TRANS_F32", "Counter_Value": 9.0 * units / 64})
+    with open(d / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    out = bench.summarise_counters(str(tmp_path / "pmc"), "c2-fp32", "cmd", mad_per_unit=17.25)
+    assert abs(out["per_unit"]["valu"] - 110.0) < 1e-9 and abs(out["per_unit"]["transcendental_f32"] - 9.0) < 1e-9
+    assert out["per_unit"]["mad_u64_u32"] == 17.25 and out["dispatches"] == 3
+    assert out["kernel_source_sha"] == bench.kernel_source_hash("c2-fp32")
+    # traffic: WRITE_SIZE of the kernel against the copy kernel's reading (KiB)
+    t = tmp_path / "traffic" / "h" / "2"
+    t.mkdir(parents=True)
+    rows = [{"Dispatch_Id": 0, "Kernel_Name": "forward_kernel<1, 4, true, false>", "Counter_Name": "WRITE_SIZE",
+             "Counter_Value": 1.2e9 / 1024 * 0.5},
+            {"Dispatch_Id": 1, "Kernel_Name": "copy_kernel(...)", "Counter_Name": "WRITE_SIZE",
+             "Counter_Value": 1.2e9 / 1024 * 0.5}]
+    with open(t / "y_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    tr = bench.summarise_counters(str(tmp_path / "traffic"), "c2-fp32", "cmd")
+    assert abs(tr["write_bytes_per_launch"] - 1.2e9) < 1e-3
+    assert abs(tr["calibration"]["write_counter_over_true"] - 0.5) < 1e-12
+    # kernel trace: two dispatches 10 us long, 5 us apart
+    k = tmp_path / "trace" / "h" / "3"
+    k.mkdir(parents=True)
+    rows = [{"Kernel_Name": "batched_kernel<1, 4, false>(...)", "Start_Timestamp": s, "End_Timestamp": s + 10_000}
+            for s in (0, 15_000, 30_000)]
+    with open(k / "z_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    md = bench.summarise_trace(str(tmp_path / "trace"), "c4-graph", "cmd")
+    assert "| kernel duration | 10.00 |" in md and "| idle gap to the next dispatch | 5.00 |" in md
 
 
 def test_more_than_one_gpu_is_refused():
