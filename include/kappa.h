@@ -258,6 +258,29 @@ KAPPA_API kappa_status kappa_sample_backward(double kappa, double theta, uint64_
                                    const void *gx, const void *gy, const void *gz, double *grad,
                                    void *workspace, size_t workspace_bytes, void *stream);
 
+/* kappa_sample_backward_noalloc -- kappa_sample_backward without a workspace
+ * argument, for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels, results (bit for bit) and errors as
+ * kappa_sample_backward, except that the partial sums go to a static device
+ * array of the library: KAPPA_BACKWARD_SCRATCH_BYTES (64 KiB, one FP64 pair
+ * per workgroup of the backward grid) on each device, held from the first
+ * call on that device until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); its first call on a
+ * device looks the array's address up once (hipGetSymbolAddress).  Every
+ * call on one device shares that device's array: calls whose launches
+ * overlap in time on one device (other streams, other host threads) race on
+ * it and may return wrong sums; serialise them.  Each call writes every
+ * partial it reads, so nothing needs clearing between calls.  KAPPA_ERANGE
+ * when the backward grid for n needs more partials than the array holds
+ * (only when the KAPPA_BACKWARD_GRID environment variable raises the grid
+ * above its default cap of 4096 workgroups).  Asynchronous. */
+#define KAPPA_BACKWARD_SCRATCH_BYTES 65536u
+KAPPA_API kappa_status kappa_sample_backward_noalloc(double kappa, double theta, uint64_t n, uint64_t seed,
+                                                     uint64_t counter_offset, uint32_t seg_id, int precision,
+                                                     const void *gx, const void *gy, const void *gz,
+                                                     double *grad, void *stream);
+
 /* kappa_load_particles -- one-shot fused particle loading: kappa_plan_create,
  * kappa_plan_set_cells and kappa_plan_launch_pic, then waits for the stream
  * and frees the plan.  cells: host array of nseg boxes. */

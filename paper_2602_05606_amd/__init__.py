@@ -17,7 +17,7 @@ from ._lib import FP32, FP32_NOTAIL, FP64, Cell, KappaError, Segment
 
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
-    "KappaSample", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
+    "KappaSample", "sample_backward_noalloc", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
     "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "issue_cost", "ISSUE_CLASSES",
     "transcendental_probe", "TRANSCENDENTALS", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
     "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell", "SEGMENT_DTYPE", "segment_table",
@@ -127,6 +127,27 @@ def sample_backward(kappa, theta, n, seed, gx, gy, gz, *, counter_offset=0, seg_
                                            _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(grad), _ptr(workspace),
                                            workspace.numel() * workspace.element_size(), _stream(stream, dev))
     _lib.check(st, "kappa_sample_backward")
+    return grad
+
+
+def sample_backward_noalloc(kappa, theta, n, seed, gx, gy, gz, grad, *, counter_offset=0, seg_id=0,
+                            precision=FP32, stream=None):
+    """sample_backward through kappa_sample_backward_noalloc: no workspace
+    (the library's static per-device partial-sum array), and the result
+    written into `grad` (a contiguous float64 device tensor of 2 elements,
+    returned).  Calls that overlap on one device race on that array."""
+    torch = _torch()
+    dt = _dtype(precision)
+    g = (gx, gy, gz)
+    for t in g:
+        if t.dtype != dt or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"upstream gradients must be contiguous {dt} with {n} elements")
+    if grad.dtype != torch.float64 or grad.numel() < 2 or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float64 tensor of at least 2 elements")
+    st = _lib.load().kappa_sample_backward_noalloc(float(kappa), float(theta), n, seed, counter_offset, seg_id,
+                                                   precision, _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(grad),
+                                                   _stream(stream, gx.device))
+    _lib.check(st, "kappa_sample_backward_noalloc")
     return grad
 
 

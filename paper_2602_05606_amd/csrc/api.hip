@@ -325,6 +325,26 @@ kappa_status kappa_sample_backward(double kappa, double theta, uint64_t n, uint6
                            static_cast<double *>(workspace), stream);
 }
 
+kappa_status kappa_sample_backward_noalloc(double kappa, double theta, uint64_t n, uint64_t seed,
+                                           uint64_t counter_offset, uint32_t seg_id, int precision, const void *gx,
+                                           const void *gy, const void *gz, double *grad, void *stream)
+{
+    kappa_status st = backward_checks(kappa, theta, n, counter_offset, precision, gx, gy, gz, grad);
+    if (st != KAPPA_OK) return st;
+    const size_t need = static_cast<size_t>(backward_grid(n)) * 2 * sizeof(double);
+    if (need > backward_scratch_bytes())
+        return fail(KAPPA_ERANGE, "the backward launch for n = %llu needs %zu bytes of partial sums, more than the "
+                                  "%zu of the library's static scratch (KAPPA_BACKWARD_GRID raised the grid)",
+                    (unsigned long long)n, need, backward_scratch_bytes());
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    double *partials = nullptr;
+    st = check_hip(backward_scratch(&partials), "hipGetSymbolAddress of the backward scratch");
+    if (st != KAPPA_OK) return st;
+    return backward_launch(kappa, theta, n, seed, counter_offset, seg_id, precision, gx, gy, gz, grad, partials,
+                           stream);
+}
+
 kappa_status kappa_philox(uint64_t n, uint64_t seed, uint64_t counter_offset, uint32_t seg_id, uint32_t draw,
                           uint32_t *out, void *stream)
 {

@@ -14,6 +14,7 @@
 // and writes one pair of FP64 partial sums per block; a second one-block
 // kernel adds the partials in a fixed order.
 #include <cstdlib>
+#include <mutex>
 
 #include "kappa_device.hpp"
 #include "kappa_internal.hpp"
@@ -24,6 +25,18 @@ namespace {
 
 constexpr int kBwdBlock = 256;
 constexpr int kBwdMaxGrid = 4096;
+
+// Partial sums of kappa_sample_backward_noalloc: one FP64 pair per workgroup
+// of the default grid (at most kBwdMaxGrid), 64 KiB per device, held from the
+// library's load until the process ends.  Host code never passes this name
+// to a kernel: it is a host-side stand-in for the device array, whose address
+// on each device comes from hipGetSymbolAddress (backward_scratch).
+static __device__ __align__(256) double scratch[2 * kBwdMaxGrid];
+static_assert(sizeof(scratch) == KAPPA_BACKWARD_SCRATCH_BYTES, "the header states the scratch size");
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kScratchDevices] = {};
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -277,6 +290,26 @@ int backward_grid(uint64_t n)
         else if (v > 0 && v <= (1 << 20)) cap = static_cast<uint64_t>(v);
     }
     return static_cast<int>(need < 1 ? 1 : (need > cap ? cap : need));
+}
+
+size_t backward_scratch_bytes() { return sizeof(scratch); }
+
+hipError_t backward_scratch(double **ptr)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        // with dev current: each device holds its own copy of the array
+        void *p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess) return err;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStream_t stream)

@@ -77,6 +77,11 @@ struct BwdArgs {
 };
 
 int backward_grid(uint64_t n);  // number of partial blocks for n particles
+// The library's static partial-sum buffer for the allocation-free backward
+// entry point: its size, and its device address on the current device (looked
+// up once per device with hipGetSymbolAddress, then cached).
+size_t backward_scratch_bytes();
+hipError_t backward_scratch(double **ptr);
 hipError_t launch_backward(int mode, const BwdArgs &args, double *grad, hipStream_t stream);
 
 // ---- exact baselines ------------------------------------------------------

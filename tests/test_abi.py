@@ -307,3 +307,24 @@ def test_segment_table_layout_and_limit():
     h = ctypes.c_void_p()
     assert lib.kappa_plan_create(view, (1 << 24) + 1, 0, 1, ctypes.byref(h)) == _lib.ERANGE
 
+
+def test_backward_noalloc_argument_checks(monkeypatch):
+    """The allocation-free backward validates like kappa_sample_backward and
+    refuses a grid whose partials exceed its static array, before any HIP call."""
+    lib = _lib.load()
+    FAKE = ctypes.c_void_p(0x10000)
+    n = 1 << 20
+    assert lib.kappa_sample_backward_noalloc(1.2, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward_noalloc(3.0, 0.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward_noalloc(3.0, 1.0, n, 0, 0, 0, 7, FAKE, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward_noalloc(3.0, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward_noalloc(3.0, 1.0, n, 0, 0, 0, 1, None, FAKE, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.kappa_sample_backward_noalloc(3.0, 1.0, n, 0, 0, 0, 1, ctypes.c_void_p(0x10002), FAKE, FAKE, FAKE,
+                                             None) == _lib.EALIGN
+    assert lib.kappa_sample_backward_noalloc(math.inf, 1.0, n, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE,
+                                             None) == _lib.EINVAL
+    # a grid of 8192 partial blocks (2^23 particles at 1024 per block) needs 128 KiB: more than the 64 KiB array
+    monkeypatch.setenv("KAPPA_BACKWARD_GRID", "8192")
+    assert lib.kappa_sample_backward_noalloc(3.0, 1.0, 1 << 23, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE,
+                                             None) == _lib.ERANGE
+    assert "static scratch" in lib.kappa_last_error().decode()
