@@ -52,14 +52,19 @@ KERNELS["c4-graph"] = dict(KERNELS["c4-direct"])
 # VALU issue capacity: 256 CUs x 4 SIMDs, 2.4 GHz at most.  Issue floor of one
 # wave64 instruction in SIMD-cycles, from the chip's published vector rates:
 # full-rate 32-bit operations 2 (64 lanes at 32 per cycle: the 157.3 TFLOP/s
-# FP32 vector peak), FP64 arithmetic 4 (78.6 TFLOP/s), v_mad_u64_u32 4 (half
-# rate), single-precision transcendentals 8 (quarter rate).  Priced at these
-# floors an instruction mix cannot exceed the chip's capacity: the fraction is
-# a lower bound on the share of issue time the kernel needs.  The issue probe's
-# measured costs (all a little above the floors) are reported beside it.
+# FP32 vector peak), FP64 arithmetic 4 (78.6 TFLOP/s), 64-bit integer
+# operations such as v_mad_u64_u32 4 (two passes), transcendentals 8 (quarter
+# rate).  Priced at these floors an instruction mix cannot exceed the chip's
+# capacity: the fraction is a lower bound on the share of issue time the
+# kernel needs.  The issue probe's measured costs (all a little above the
+# floors) are reported beside it.
 SIMD_COUNT = 256 * 4
 SIMD_CYCLES_PER_S = SIMD_COUNT * 2.4e9
-ISSUE_FLOOR = {"full_rate": 2.0, "f64": 4.0, "mad_u64_u32": 4.0, "transcendental_f32": 8.0}
+ISSUE_FLOOR = {"full_rate": 2.0, "f64": 4.0, "int64": 4.0, "transcendental_f32": 8.0, "transcendental_f64": 8.0}
+# rocprofv3 instruction classes (SQ_INSTS_VALU_*) of each priced class
+VALU_CLASSES = {"transcendental_f32": ["SQ_INSTS_VALU_TRANS_F32"], "transcendental_f64": ["SQ_INSTS_VALU_TRANS_F64"],
+                "f64": ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64"],
+                "int64": ["SQ_INSTS_VALU_INT64"]}
 
 
 def log(msg):
@@ -117,11 +122,8 @@ def alu_roofline(units_per_s, clock=None, costs=None, path="c2-fp32", profile=No
     if v is None:
         return None
     pu = v["per_unit"]
-    trans = pu.get("transcendental_f32", 0.0)
-    f64 = pu.get("f64", 0.0)
-    mad = pu.get("mad_u64_u32", 0.0)
-    full = pu["valu"] - trans - f64 - mad
-    mix = {"full_rate": full, "f64": f64, "mad_u64_u32": mad, "transcendental_f32": trans}
+    mix = {k: pu.get(k, 0.0) for k in VALU_CLASSES}
+    mix["full_rate"] = pu["valu"] - sum(mix.values())
     cycles = sum(ISSUE_FLOOR[k] * n for k, n in mix.items()) / 64.0
     achieved = units_per_s * cycles
     out = {"bound": "alu", "achieved": achieved, "peak": SIMD_CYCLES_PER_S, "unit": "SIMD-cycles/s",
@@ -488,15 +490,20 @@ PROFILE_PATHS = ("c1-fp64", "c2-fp32", "c2-fp64", "c3-fp32", "c3-fp64", "c4-dire
                  "c4-pic", "copy", "store-fp32", "store-fp64", "exact-t", "exact-pareto")
 
 
-def _rocprof_rows(directory, suffix):
-    """Rows of every rocprofv3 CSV under directory whose name ends in suffix."""
+def _rocprof_rows(directories, suffix):
+    """Rows of every rocprofv3 CSV whose name ends in suffix under the
+    directories (one path, or several joined by commas: the passes of one
+    measurement, e.g. FETCH_SIZE and WRITE_SIZE)."""
     import csv
     rows = []
-    for root, _, files in os.walk(directory):
-        for f in sorted(files):
-            if f.endswith(suffix):
-                with open(os.path.join(root, f), newline="") as fh:
-                    rows += list(csv.DictReader(fh))
+    for directory in directories.split(","):
+        for root, _, files in os.walk(directory):
+            for f in sorted(files):
+                if f.endswith(suffix):
+                    with open(os.path.join(root, f), newline="") as fh:
+                        for r in csv.DictReader(fh):
+                            r["_pass"] = directory
+                            rows.append(r)
     return rows
 
 
@@ -529,10 +536,10 @@ def summarise_counters(directory, path, command, mad_per_unit=None, note=None):
         who = "kernel" if k["match"] in name else "copy" if "copy_kernel" in name else None
         if who is None:
             continue
-        key = (who, r["Counter_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        key = (who, r["Counter_Name"], r["_pass"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
         sums[key] = sums.get(key, 0.0) + float(r["Counter_Value"])
     per = {}
-    for (who, cname, _), v in sums.items():
+    for (who, cname, _, _), v in sums.items():
         per.setdefault((who, cname), []).append(v)
     mean = {key: sum(v) / len(v) for key, v in per.items()}
     units = _path_units(path)
@@ -557,16 +564,16 @@ def summarise_counters(directory, path, command, mad_per_unit=None, note=None):
         out["algorithmic_bytes_per_launch"] = k["unit_bytes"] * units
         out["algorithmic_direction"] = k["traffic"]
     else:
+        # wave instructions x 64 lanes / particles: instructions per particle
         pu = {"valu": counters["SQ_INSTS_VALU"] * 64.0 / units}
-        if "SQ_INSTS_VALU_TRANS_F32" in counters:
-            pu["transcendental_f32"] = counters["SQ_INSTS_VALU_TRANS_F32"] * 64.0 / units
-        f64 = [c for c in counters if c.startswith("SQ_INSTS_VALU_") and c.endswith("_F64")]
-        if f64:
-            pu["f64"] = sum(counters[c] for c in f64) * 64.0 / units
-            pu["f64_counters"] = f64
+        for cls, names in VALU_CLASSES.items():
+            if any(c in counters for c in names):
+                pu[cls] = sum(counters.get(c, 0.0) for c in names) * 64.0 / units
         if mad_per_unit is not None:
-            pu["mad_u64_u32"] = float(mad_per_unit)
+            pu["mad_u64_u32_isa"] = float(mad_per_unit)
         out["per_unit"] = pu
+        if "GRBM_GUI_ACTIVE" in counters:
+            out["grbm_gui_active_per_dispatch"] = counters["GRBM_GUI_ACTIVE"]
     if note:
         out["notes"] = note
     return out

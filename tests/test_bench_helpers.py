@@ -26,13 +26,13 @@ def test_sup_G_minus_F_against_the_oracle(orc, kappa):
 
 def test_alu_roofline_prices_at_the_issue_floors():
     """The VALU-issue roofline prices each instruction class at its issue
-    floor (full rate 2, FP64 and v_mad_u64_u32 4, FP32 transcendentals 8
+    floor (full rate 2, FP64 and 64-bit integer 4, transcendentals 8
     SIMD-cycles per wave64 instruction), so a kernel issuing at the chip's
     capacity reaches exactly 1."""
-    prof = {"per_unit": {"valu": 115.0, "transcendental_f32": 9.0, "mad_u64_u32": 17.25}}
+    prof = {"per_unit": {"valu": 115.0, "transcendental_f32": 9.0, "int64": 20.0}}
     r = bench.alu_roofline(3.5e11, {"core_clock_ghz": 2.0}, None, profile=prof)
-    full = 115.0 - 9.0 - 17.25
-    want = (2 * full + 8 * 9.0 + 4 * 17.25) / 64
+    full = 115.0 - 9.0 - 20.0
+    want = (2 * full + 8 * 9.0 + 4 * 20.0) / 64
     assert abs(r["simd_cycles_per_unit_at_floor"] - want) < 1e-12
     assert abs(r["frac"] - 3.5e11 * want / bench.SIMD_CYCLES_PER_S) < 1e-12
     assert abs(r["frac_at_measured_clock"] - 3.5e11 * want / (1024 * 2.0e9)) < 1e-12
@@ -41,9 +41,10 @@ def test_alu_roofline_prices_at_the_issue_floors():
     assert abs(bench.alu_roofline(full_rate, {"core_clock_ghz": 2.0}, None, profile=prof)["frac_at_measured_clock"]
                - 1.0) < 1e-12
     # an FP64 mix
-    prof64 = {"per_unit": {"valu": 300.0, "f64": 150.0, "mad_u64_u32": 17.25}}
+    prof64 = {"per_unit": {"valu": 300.0, "f64": 150.0, "transcendental_f64": 5.0, "int64": 23.5}}
     r64 = bench.alu_roofline(1e11, None, None, profile=prof64)
-    assert abs(r64["simd_cycles_per_unit_at_floor"] - (2 * (300 - 150 - 17.25) + 4 * 150 + 4 * 17.25) / 64) < 1e-12
+    want64 = (2 * (300 - 150 - 5 - 23.5) + 4 * 150 + 8 * 5 + 4 * 23.5) / 64
+    assert abs(r64["simd_cycles_per_unit_at_floor"] - want64) < 1e-12
 
 
 def test_summarise_counters_and_trace(tmp_path):
@@ -60,13 +61,15 @@ def test_summarise_counters_and_trace(tmp_path):
                      "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 110.0 * units / 64})
         rows.append({"Dispatch_Id": disp, "Kernel_Name": "void kappa::forward_kernel<1, 4, true, false>(...)",
                      "Counter_Name": "SQ_INSTS_VALU_TRANS_F32", "Counter_Value": 9.0 * units / 64})
+        rows.append({"Dispatch_Id": disp, "Kernel_Name": "void kappa::forward_kernel<1, 4, true, false>(...)",
+                     "Counter_Name": "SQ_INSTS_VALU_INT64", "Counter_Value": 20.0 * units / 64})
     with open(d / "x_counter_collection.csv", "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=list(rows[0]))
         w.writeheader()
         w.writerows(rows)
-    out = bench.summarise_counters(str(tmp_path / "pmc"), "c2-fp32", "cmd", mad_per_unit=17.25)
+    out = bench.summarise_counters(str(tmp_path / "pmc"), "c2-fp32", "cmd")
     assert abs(out["per_unit"]["valu"] - 110.0) < 1e-9 and abs(out["per_unit"]["transcendental_f32"] - 9.0) < 1e-9
-    assert out["per_unit"]["mad_u64_u32"] == 17.25 and out["dispatches"] == 3
+    assert abs(out["per_unit"]["int64"] - 20.0) < 1e-9 and out["dispatches"] == 3
     assert out["kernel_source_sha"] == bench.kernel_source_hash("c2-fp32")
     # traffic: WRITE_SIZE of the kernel against the copy kernel's reading (KiB)
     t = tmp_path / "traffic" / "h" / "2"
