@@ -935,9 +935,10 @@ def main():
             default_shape = plan.shape
             plan.launch(outb)
             tuned = plan.autotune(outb, reps=5)
-            direct_ms = time_launches(lambda: plan.launch(outb), 20, torch)
+            # launches of 20-50 us: 200 back to back, after 20 untimed
+            direct_ms = time_launches(lambda: plan.launch(outb), 200, torch, warm=20)
             plan.graph_launch(outb)
-            graph_ms = time_launches(lambda: plan.graph_launch(outb), 20, torch)
+            graph_ms = time_launches(lambda: plan.graph_launch(outb), 200, torch, warm=20)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(50):
@@ -959,18 +960,18 @@ def main():
             with torch.cuda.graph(caller_graph):
                 for b in caller_bufs:
                     plan.launch(b)
-            caller_ms = time_launches(caller_graph.replay, 10, torch) / len(caller_bufs)
+            caller_ms = time_launches(caller_graph.replay, 50, torch, warm=5) / len(caller_bufs)
             del caller_graph, caller_bufs
             # the single-species kernel on the same number of particles, for comparison
-            single_ms = time_launches(lambda: kp.sample(3.0, 1.0, plan.total, 4, precision=kp.FP32, out=outb), 20,
-                                      torch)
+            single_ms = time_launches(lambda: kp.sample(3.0, 1.0, plan.total, 4, precision=kp.FP32, out=outb), 200,
+                                      torch, warm=20)
             # fused particle loading: positions in each cell's box with the velocities
             plan.set_cells(workloads.batched_cells())
             posb = plan.outputs()
             plan.launch_pic(posb, outb)
-            pic_ms = time_launches(lambda: plan.launch_pic(posb, outb), 20, torch)
+            pic_ms = time_launches(lambda: plan.launch_pic(posb, outb), 200, torch, warm=20)
             plan.graph_launch_pic(posb, outb)
-            pic_graph_ms = time_launches(lambda: plan.graph_launch_pic(posb, outb), 20, torch)
+            pic_graph_ms = time_launches(lambda: plan.graph_launch_pic(posb, outb), 200, torch, warm=20)
             extras["batched_c4"] = {"particles": plan.total, "segments": len(segs), "default_shape": default_shape,
                                     "tuned_shape": tuned, "direct_launch_ms": direct_ms, "graph_launch_ms": graph_ms,
                                     "graph_wall_ms": wall_ms, "particles_per_s": plan.total / (graph_ms * 1e-3),

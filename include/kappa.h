@@ -130,6 +130,27 @@ KAPPA_API kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint
                           uint64_t counter_offset, uint32_t seg_id, int precision,
                           void *vx, void *vy, void *vz, void *stream);
 
+/* kappa_sample_autotune -- time kappa_sample's launch shapes (256, 128 or 64
+ * threads per workgroup x 1, 2, 4 or 8 particles per thread) on n particles
+ * of the given precision into vx, vy, vz (written; 16-byte aligned, else
+ * KAPPA_EALIGN), `reps` timed launches each after one warm-up (HIP events on
+ * stream), and keep the fastest for this precision and every n in the same
+ * power-of-two bucket: later kappa_sample calls of this process use it, and it
+ * is recorded in the autotune cache file (KAPPA_AUTOTUNE_CACHE; see below).
+ * block, unroll (host, may be NULL) receive the chosen shape.  The output of
+ * kappa_sample never depends on the shape.  Synchronous.
+ *
+ * Environment of the tuned shapes (single-species and plans):
+ *   KAPPA_AUTOTUNE_CACHE=<path>  JSON file of tuned shapes shared by processes;
+ *   KAPPA_AUTOTUNE=off|use|refresh  off: the file is neither read nor
+ *       written; use (default): launches start from the file's shape and
+ *       tuning writes it; refresh: the file is not read, tuning writes it;
+ *   KAPPA_FORWARD_SHAPE="block,unroll" overrides kappa_sample's shape;
+ *   KAPPA_LOG=1  one line on stderr per kernel launch (kernel, precision,
+ *       particles, grid, block, particles per thread, stream). */
+KAPPA_API kappa_status kappa_sample_autotune(int precision, uint64_t n, void *vx, void *vy, void *vz, int reps,
+                                             int *block, int *unroll, void *stream);
+
 /* One segment of a batched launch: a species (kappa, theta) in one cell
  * (drift) with count particles.  Its particles use counters
  * (0 .. count-1, seg_id, 0), so segment s of a batched call equals

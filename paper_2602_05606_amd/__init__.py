@@ -17,7 +17,7 @@ from ._lib import FP32, FP32_NOTAIL, FP64, Cell, KappaError, Segment
 
 __all__ = [
     "FP64", "FP32", "FP32_NOTAIL", "KappaError", "Segment", "params", "sample", "sample_backward",
-    "KappaSample", "sample_backward_noalloc", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
+    "KappaSample", "sample_backward_noalloc", "sample_autotune", "philox", "Plan", "sample_batched", "sample_exact_t", "sample_exact_pareto",
     "fill_probe", "copy_probe", "clock_probe", "clock_probe_stamps", "core_clock_hz", "issue_cost", "ISSUE_CLASSES",
     "transcendental_probe", "TRANSCENDENTALS", "backward_workspace_bytes", "version", "library_path", "speed_histogram",
     "relative_entropy", "divergence_grid", "optimum_c", "load_particles", "Cell", "SEGMENT_DTYPE", "segment_table",
@@ -99,6 +99,17 @@ def sample(kappa, theta, n, seed, *, counter_offset=0, seg_id=0, precision=FP32,
                                   _ptr(vx), _ptr(vy), _ptr(vz), _stream(stream, vx.device))
     _lib.check(st, "kappa_sample")
     return vx, vy, vz
+
+
+def sample_autotune(n, precision=FP32, reps=5, out=None, device=None, stream=None):
+    """Times kappa_sample's launch shapes on n particles and keeps the fastest
+    for this precision and size bucket (kappa_sample_autotune); returns
+    (block, particles per thread)."""
+    vx, vy, vz = _outputs(n, precision, out, device)
+    b, u = ctypes.c_int(), ctypes.c_int()
+    _lib.check(_lib.load().kappa_sample_autotune(precision, n, _ptr(vx), _ptr(vy), _ptr(vz), reps, ctypes.byref(b),
+                                                 ctypes.byref(u), _stream(stream, vx.device)), "kappa_sample_autotune")
+    return b.value, u.value
 
 
 def backward_workspace_bytes(n):

@@ -219,6 +219,59 @@ kappa_status kappa_sample(double kappa, double theta, uint64_t n, uint64_t seed,
     return check_hip(launch_forward(precision, shape, vec, a, s), "forward kernel launch");
 }
 
+kappa_status kappa_sample_autotune(int precision, uint64_t n, void *vx, void *vy, void *vz, int reps, int *block,
+                                   int *unroll, void *stream)
+{
+    if (!precision_ok(precision)) return fail(KAPPA_EINVAL, "unknown precision %d", precision);
+    if (n == 0) return fail(KAPPA_EINVAL, "n must be at least 1");
+    if (reps < 1) return fail(KAPPA_EINVAL, "reps must be at least 1 (got %d)", reps);
+    kappa_status st = check_outputs(n, precision, vx, vy, vz);
+    if (st != KAPPA_OK) return st;
+    if (!vec_aligned(precision, vx, vy, vz))
+        return fail(KAPPA_EALIGN, "the autotuner times the vector-store kernels: outputs must be 16-byte aligned");
+    st = require_device();
+    if (st != KAPPA_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the cost per particle barely depends on kappa, theta or the counters
+    const FwdArgs a = forward_args(3.0, 1.0, n, 0, 0, 0, vx, vy, vz);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (st == KAPPA_OK) st = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    Shape best = forward_shape(precision, n, true, false);
+    float best_ms = 3.4e38f;
+    const int blocks[] = {64, 128, 256};
+    const int unrolls[] = {1, 2, 4, 8};
+    for (int b : blocks) {
+        for (int u : unrolls) {
+            if (st != KAPPA_OK) break;
+            Shape c{b, u, 1};
+            const uint64_t need = ((n + u - 1) / u + b - 1) / b;
+            const uint64_t cap = forward_max_grid();
+            c.grid = static_cast<int>(need < cap ? need : cap);
+            st = check_hip(launch_forward(precision, c, true, a, s), "autotune warm-up launch");
+            if (st != KAPPA_OK) break;
+            st = check_hip(hipEventRecord(e0, s), "hipEventRecord");
+            for (int r = 0; r < reps && st == KAPPA_OK; ++r)
+                st = check_hip(launch_forward(precision, c, true, a, s), "autotune launch");
+            if (st == KAPPA_OK) st = check_hip(hipEventRecord(e1, s), "hipEventRecord");
+            if (st == KAPPA_OK) st = check_hip(hipEventSynchronize(e1), "autotune synchronize");
+            float ms = 0.f;
+            if (st == KAPPA_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (st == KAPPA_OK && ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != KAPPA_OK) return st;
+    set_forward_tuned(precision, n, best);
+    if (block) *block = best.block;
+    if (unroll) *unroll = best.unroll;
+    return KAPPA_OK;
+}
+
 kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t seed, uint64_t counter_offset,
                                uint32_t seg_id, int precision, void *vx, void *vy, void *vz, uint64_t *stamps,
                                uint64_t stamps_len, uint32_t *blocks, double *wall_hz, void *stream)
@@ -237,7 +290,7 @@ kappa_status kappa_clock_probe(double kappa, double theta, uint64_t n, uint64_t 
         return fail(KAPPA_EALIGN, "the clock probe times the vector-store kernel: outputs must be 16-byte aligned");
     if (!stamps) return fail(KAPPA_EINVAL, "null stamps pointer");
     if (reinterpret_cast<uintptr_t>(stamps) % 8) return fail(KAPPA_EALIGN, "stamps must be 8-byte aligned");
-    const Shape shape = forward_shape(precision, n, true);
+    const Shape shape = forward_shape(precision, n, true, false);
     if (shape.unroll != forward_default_unroll(precision))
         return fail(KAPPA_EINVAL, "the clock probe times the default shape (KAPPA_FORWARD_SHAPE overrides the unroll)");
     if (static_cast<uint64_t>(shape.grid) * shape.block * shape.unroll < n)

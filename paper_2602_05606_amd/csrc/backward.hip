@@ -259,6 +259,7 @@ hipError_t launch_mode(const BwdArgs &a, bool vec, hipStream_t stream)
 {
     constexpr int U = unroll_for(MODE);
     const int grid = backward_grid(a.n);
+    log_launch("backward_kernel", MODE, a.n, Shape{kBwdBlock, vec ? U : 1, grid}, stream);
     if (vec)
         hipLaunchKernelGGL((backward_kernel<MODE, U, true, HI_UNIFORM>), dim3(grid), dim3(kBwdBlock), 0, stream, a);
     else

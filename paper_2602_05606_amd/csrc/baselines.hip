@@ -201,6 +201,8 @@ hipError_t launch_exact(void (*kernel)(ExactArgs), const ExactArgs &a, hipStream
 {
     const uint64_t groups = (a.n + U - 1) / U;
     const uint64_t grid = (groups + 255) / 256;
+    log_launch("exact_kernel", sizeof(T) == 8 ? kModeF64 : kModeF32, a.n, Shape{256, U, static_cast<int>(grid)},
+               stream);
     hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid > 0 ? grid : 1)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

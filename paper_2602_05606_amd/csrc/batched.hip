@@ -8,7 +8,10 @@
 // of U consecutive particles finds its segment by a binary search restricted
 // to its tile's segment range.  Particle j of segment s uses the counter
 // (j - start[s], seg_id[s]), so a segment's samples equal a single-species
-// call with the same seed and seg_id, whatever the launch shape.
+// call with the same seed and seg_id, whatever the launch shape.  The device
+// tables hold pieces of at most 2^32 particles (a longer segment is split),
+// each with the Philox words its counters share through the first two rounds
+// (SegWords), so a particle's block takes 18 products instead of 20.
 //
 // The launch can be captured once into a hipGraph and replayed; the shape
 // (block, particles per thread, grid) is chosen by a timing sweep.
@@ -67,7 +70,7 @@ struct BatchArgs {
     const uint32_t *tile;    // ntiles + 1
     const SegF32 *seg32;     // nseg
     const SegF64 *seg64;     // nseg
-    const uint32_t *seg_ids; // nseg
+    const SegWords *words;   // nseg
     const CellF32 *cell32;   // nseg, positions only
     const CellF64 *cell64;   // nseg, positions only
     void *vx, *vy, *vz;
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
         const uint64_t t = j0 / kTile;
         uint32_t s = find_segment(a.start, a.tile[t], a.tile[t + 1], j0);
         uint64_t seg_begin = a.start[s], seg_next = a.start[s + 1];  // s + 1 <= nseg
-        uint32_t seg_id = a.seg_ids[s];
+        SegWords wd = a.words[s];
         SegParams<MODE> prm;
         prm.load(a, s);
         CellParams<MODE> cell;
@@ -167,18 +170,20 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                     seg_next = a.start[s + 1];
                 } while (j >= seg_next);
                 seg_begin = a.start[s];
-                seg_id = a.seg_ids[s];
+                wd = a.words[s];
                 prm.load(a, s);
                 if constexpr (POS) cell.load(a, s);
             }
             seg_of[k] = s;
+            // the piece holds at most 2^32 particles: j - seg_begin is the counter's low word
+            const uint32_t c0 = static_cast<uint32_t>(j - seg_begin);
             if constexpr (POS) {
-                const Block4 bp = particle_block(j - seg_begin, seg_id, 1, a.k0, a.k1);
+                const Block4 bp = philox4x32_10_seg(c0, 1, wd, a.k0, a.k1);
                 qx[k] = cell.coord(0, bp.r0);
                 qy[k] = cell.coord(1, bp.r1);
                 qz[k] = cell.coord(2, bp.r2);
             }
-            const Block4 b = particle_block(j - seg_begin, seg_id, 0, a.k0, a.k1);
+            const Block4 b = philox4x32_10_seg(c0, 0, wd, a.k0, a.k1);
             const auto &q = prm.q;
             if constexpr (MODE == kModeF64) {
                 SpeciesF64 sp{q.kstar, q.inv_kstar, q.a, q.b, q.c, q.two_b, q.neg_four_b, q.theta, 0, 0, 0};
@@ -208,7 +213,8 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
                         const SegF64 w = a.seg64[sq];
                         const SegF32 f = a.seg32[sq];
                         const SpeciesF64 s64{w.kstar, w.inv_kstar, w.a, w.b, w.c, w.two_b, w.neg_four_b, w.theta, 0, 0, 0};
-                        const Block4 b = particle_block(j0 + k - a.start[sq], a.seg_ids[sq], 0, a.k0, a.k1);
+                        const Block4 b =
+                            philox4x32_10_seg(static_cast<uint32_t>(j0 + k - a.start[sq]), 0, a.words[sq], a.k0, a.k1);
                         tail_particle_f32(b, s64, x[k], y[k], z[k]);
                         x[k] += f.dx;
                         y[k] += f.dy;
@@ -231,6 +237,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
 template <int MODE, bool POS>
 hipError_t launch_batched_mode(const Shape &sh, const BatchArgs &a, hipStream_t stream)
 {
+    log_launch(POS ? "batched_kernel+positions" : "batched_kernel", MODE, a.total, sh, stream);
     dim3 grid(sh.grid), block(sh.block);
     switch (sh.unroll) {
     case 1: hipLaunchKernelGGL((batched_kernel<MODE, 1, POS>), grid, block, 0, stream, a); break;
@@ -265,47 +272,6 @@ bool shape_valid(const Shape &s)
     return b && u && s.grid >= 1 && s.grid <= (1 << 23);
 }
 
-// ---- autotune cache: a flat JSON object {"key": "block,unroll,grid", ...} ----
-std::mutex g_cache_mutex;
-
-std::map<std::string, std::string> read_cache(const char *path)
-{
-    std::map<std::string, std::string> m;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return m;
-    std::string text;
-    char buf[4096];
-    size_t got;
-    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
-    std::fclose(f);
-    // parse "k": "v" pairs
-    size_t pos = 0;
-    while (true) {
-        size_t k0 = text.find('"', pos);
-        if (k0 == std::string::npos) break;
-        size_t k1 = text.find('"', k0 + 1);
-        size_t v0 = text.find('"', k1 + 1);
-        size_t v1 = v0 == std::string::npos ? v0 : text.find('"', v0 + 1);
-        if (k1 == std::string::npos || v1 == std::string::npos) break;
-        m[text.substr(k0 + 1, k1 - k0 - 1)] = text.substr(v0 + 1, v1 - v0 - 1);
-        pos = v1 + 1;
-    }
-    return m;
-}
-
-void write_cache(const char *path, const std::map<std::string, std::string> &m)
-{
-    std::string tmp = std::string(path) + ".tmp";
-    FILE *f = std::fopen(tmp.c_str(), "w");
-    if (!f) return;
-    std::fprintf(f, "{\n");
-    size_t i = 0;
-    for (const auto &kv : m) std::fprintf(f, "  \"%s\": \"%s\"%s\n", kv.first.c_str(), kv.second.c_str(), ++i < m.size() ? "," : "");
-    std::fprintf(f, "}\n");
-    std::fclose(f);
-    std::rename(tmp.c_str(), path);
-}
-
 std::string cache_key(int mode, uint64_t total, uint32_t nseg)
 {
     // bucket by powers of two of the total and the segment count
@@ -325,7 +291,9 @@ struct kappa_plan_s {
     int device = 0;
     int mode = 0;
     uint64_t total = 0;
-    uint32_t nseg = 0;
+    uint32_t nseg = 0;   // the caller's segments
+    uint32_t npiece = 0; // device pieces: segments split at 2^32 particles
+    std::vector<uint32_t> piece_seg;  // caller's segment of each piece
     uint32_t k0 = 0, k1 = 0;
     kappa::Shape shape{256, 4, 1};
     void *dev_block = nullptr;  // one allocation holding every table
@@ -333,7 +301,7 @@ struct kappa_plan_s {
     const uint32_t *tile = nullptr;
     const kappa::SegF32 *seg32 = nullptr;
     const kappa::SegF64 *seg64 = nullptr;
-    const uint32_t *seg_ids = nullptr;
+    const kappa::SegWords *words = nullptr;
     // cell boxes for fused particle loading (kappa_plan_set_cells)
     void *cell_block = nullptr;
     const kappa::CellF32 *cell32 = nullptr;
@@ -362,12 +330,12 @@ BatchArgs batch_args(const kappa_plan_s *p, const Outputs &o)
     a.total = p->total;
     a.k0 = p->k0;
     a.k1 = p->k1;
-    a.nseg = p->nseg;
+    a.nseg = p->npiece;
     a.start = p->start;
     a.tile = p->tile;
     a.seg32 = p->seg32;
     a.seg64 = p->seg64;
-    a.seg_ids = p->seg_ids;
+    a.words = p->words;
     a.cell32 = p->cell32;
     a.cell64 = p->cell64;
     a.vx = o.v[0];
@@ -442,28 +410,47 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
         delete p;
         return st;
     }
-    // host tables
-    std::vector<uint64_t> start(nseg + 1);
-    std::vector<SegF32> s32(nseg);
-    std::vector<SegF64> s64(nseg);
-    std::vector<uint32_t> ids(nseg);
+    // host tables, one entry per piece of at most 2^32 particles
+    constexpr uint64_t kPiece = 1ull << 32;
+    std::vector<uint64_t> start;
+    std::vector<SegF32> s32;
+    std::vector<SegF64> s64;
+    std::vector<SegWords> words;
     std::map<double, Setup> setups;  // species repeat across cells: set up each kappa once
     uint64_t acc = 0;
     for (uint32_t s = 0; s < nseg; ++s) {
-        start[s] = acc;
-        acc += segs[s].count;
         auto it = setups.find(segs[s].kappa);
         if (it == setups.end()) it = setups.emplace(segs[s].kappa, make_setup(segs[s].kappa)).first;
         const SpeciesF64 a = species_f64(it->second, segs[s].theta);
         const SpeciesF32 b = species_f32(it->second, segs[s].theta);
-        s64[s] = SegF64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.two_b, a.neg_four_b, a.theta,
-                        segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
-        s32[s] = SegF32{b.inv_kstar, b.a, b.neg_c_kstar, b.four_b_kstar, b.two_kstar, b.two_b, b.theta,
-                        static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),
-                        static_cast<float>(segs[s].drift[2]), segs[s].seg_id};
-        ids[s] = segs[s].seg_id;
+        const SegF64 q64{a.kstar, a.inv_kstar, a.a, a.b, a.c, a.two_b, a.neg_four_b, a.theta,
+                         segs[s].drift[0], segs[s].drift[1], segs[s].drift[2]};
+        const SegF32 q32{b.inv_kstar, b.a, b.neg_c_kstar, b.four_b_kstar, b.two_kstar, b.two_b, b.theta,
+                         static_cast<float>(segs[s].drift[0]), static_cast<float>(segs[s].drift[1]),
+                         static_cast<float>(segs[s].drift[2]), segs[s].seg_id};
+        // piece h of the segment: counters (h 2^32 + i) for i < 2^32, whose high word h enters
+        // round 1 next to M_B seg_id
+        for (uint64_t h = 0, left = segs[s].count; h == 0 || left > 0; ++h) {
+            const uint64_t n = std::min(left, kPiece);
+            const uint64_t pb = static_cast<uint64_t>(kMulB) * segs[s].seg_id;
+            SegWords w;
+            w.c0 = static_cast<uint32_t>(pb >> 32) ^ static_cast<uint32_t>(h) ^ p->k0;
+            w.c1 = static_cast<uint32_t>(pb);
+            const uint64_t pa = static_cast<uint64_t>(kMulA) * w.c0;
+            w.pa_hi = static_cast<uint32_t>(pa >> 32);
+            w.pa_lo = static_cast<uint32_t>(pa);
+            start.push_back(acc);
+            s32.push_back(q32);
+            s64.push_back(q64);
+            words.push_back(w);
+            p->piece_seg.push_back(s);
+            acc += n;
+            left -= n;
+        }
     }
-    start[nseg] = acc;
+    const uint32_t npiece = static_cast<uint32_t>(start.size());
+    p->npiece = npiece;
+    start.push_back(acc);
     p->total = acc;
     const uint64_t ntiles = (acc + kTile - 1) / kTile;
     std::vector<uint32_t> tile(ntiles + 1);
@@ -471,18 +458,18 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
         uint32_t s = 0;
         for (uint64_t t = 0; t <= ntiles; ++t) {
             const uint64_t j = std::min<uint64_t>(t * kTile, acc > 0 ? acc - 1 : 0);
-            while (s + 1 < nseg && start[s + 1] <= j) ++s;
+            while (s + 1 < npiece && start[s + 1] <= j) ++s;
             tile[t] = s;
         }
     }
-    // one device allocation: start | tile | seg32 | seg64 | ids, each 256-byte aligned
+    // one device allocation: start | tile | seg32 | seg64 | words, each 256-byte aligned
     auto up = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
     const size_t o_start = 0;
     const size_t o_tile = o_start + up(start.size() * sizeof(uint64_t));
     const size_t o_s32 = o_tile + up(tile.size() * sizeof(uint32_t));
     const size_t o_s64 = o_s32 + up(s32.size() * sizeof(SegF32));
-    const size_t o_ids = o_s64 + up(s64.size() * sizeof(SegF64));
-    const size_t bytes = o_ids + up(ids.size() * sizeof(uint32_t));
+    const size_t o_words = o_s64 + up(s64.size() * sizeof(SegF64));
+    const size_t bytes = o_words + up(words.size() * sizeof(SegWords));
     if (hipMalloc(&p->dev_block, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
@@ -493,7 +480,7 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
     std::memcpy(host.data() + o_tile, tile.data(), tile.size() * sizeof(uint32_t));
     std::memcpy(host.data() + o_s32, s32.data(), s32.size() * sizeof(SegF32));
     std::memcpy(host.data() + o_s64, s64.data(), s64.size() * sizeof(SegF64));
-    std::memcpy(host.data() + o_ids, ids.data(), ids.size() * sizeof(uint32_t));
+    std::memcpy(host.data() + o_words, words.data(), words.size() * sizeof(SegWords));
     st = check_hip(hipMemcpy(p->dev_block, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy plan tables");
     if (st != KAPPA_OK) {
         hipFree(p->dev_block);
@@ -505,16 +492,11 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
     p->tile = reinterpret_cast<const uint32_t *>(base + o_tile);
     p->seg32 = reinterpret_cast<const SegF32 *>(base + o_s32);
     p->seg64 = reinterpret_cast<const SegF64 *>(base + o_s64);
-    p->seg_ids = reinterpret_cast<const uint32_t *>(base + o_ids);
+    p->words = reinterpret_cast<const SegWords *>(base + o_words);
     p->shape = default_batched_shape(p->mode, p->total);
-    if (const char *path = std::getenv("KAPPA_AUTOTUNE_CACHE")) {
-        std::lock_guard<std::mutex> lock(g_cache_mutex);
-        auto m = read_cache(path);
-        auto it = m.find(cache_key(p->mode, p->total, p->nseg));
+    {
         Shape s{};
-        if (it != m.end() && std::sscanf(it->second.c_str(), "%d,%d,%d", &s.block, &s.unroll, &s.grid) == 3 &&
-            shape_valid(s))
-            p->shape = s;
+        if (cache_lookup(cache_key(p->mode, p->total, p->nseg), s) && shape_valid(s)) p->shape = s;
     }
     *out = p;
     return KAPPA_OK;
@@ -679,6 +661,17 @@ extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell
                   std::isfinite(c32[s].lo[k] + c32[s].size[k])))
                 return fail(KAPPA_EINVAL, "cell %u: lo, size and lo + size must be finite as floats for an FP32 plan", s);
         }
+    // one entry per device piece (pieces of one segment share its box)
+    if (p->npiece != p->nseg) {
+        std::vector<CellF32> p32(p->npiece);
+        std::vector<CellF64> p64(p->npiece);
+        for (uint32_t v = 0; v < p->npiece; ++v) {
+            p32[v] = c32[p->piece_seg[v]];
+            p64[v] = c64[p->piece_seg[v]];
+        }
+        c32.swap(p32);
+        c64.swap(p64);
+    }
     const size_t o64 = (c32.size() * sizeof(CellF32) + 255) & ~static_cast<size_t>(255);
     const size_t bytes = o64 + c64.size() * sizeof(CellF64);
     if (hipMalloc(&p->cell_block, bytes) != hipSuccess) {
@@ -749,14 +742,7 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
                 }
             }
     p->shape = best;
-    if (const char *path = std::getenv("KAPPA_AUTOTUNE_CACHE")) {
-        std::lock_guard<std::mutex> lock(g_cache_mutex);
-        auto m = read_cache(path);
-        char val[64];
-        std::snprintf(val, sizeof val, "%d,%d,%d", best.block, best.unroll, best.grid);
-        m[cache_key(p->mode, p->total, p->nseg)] = val;
-        write_cache(path, m);
-    }
+    cache_store(cache_key(p->mode, p->total, p->nseg), best);
 done:
     hipEventDestroy(e0);
     hipEventDestroy(e1);

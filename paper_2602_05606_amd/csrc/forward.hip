@@ -112,6 +112,7 @@ namespace {
 template <int MODE, bool HI_UNIFORM>
 hipError_t launch_mode(const Shape &sh, const FwdArgs &a, hipStream_t stream)
 {
+    log_launch("forward_kernel", MODE, a.n, sh, stream);
     dim3 grid(sh.grid), block(sh.block);
     switch (sh.unroll) {
     case 1: hipLaunchKernelGGL((forward_kernel<MODE, 1, HI_UNIFORM, false>), grid, block, 0, stream, a, nullptr); break;
@@ -180,11 +181,12 @@ uint64_t forward_max_grid()
     return cap;
 }
 
-Shape forward_shape(int mode, uint64_t n, bool vec)
+Shape forward_shape(int mode, uint64_t n, bool vec, bool tuned)
 {
     Shape s;
     s.block = 256;
     s.unroll = vec ? forward_default_unroll(mode) : 1;
+    Shape t{};
     if (const char *env = std::getenv("KAPPA_FORWARD_SHAPE")) {
         int b = 0, u = 0;
         if (std::sscanf(env, "%d,%d", &b, &u) == 2 && (b == 64 || b == 128 || b == 256) &&
@@ -192,6 +194,11 @@ Shape forward_shape(int mode, uint64_t n, bool vec)
             s.block = b;
             s.unroll = vec ? u : 1;
         }
+    } else if (tuned && vec && forward_tuned(mode, n, t) && (t.block == 64 || t.block == 128 || t.block == 256) &&
+               (t.unroll == 1 || t.unroll == 2 || t.unroll == 4 || t.unroll == 8)) {
+        // a shape kappa_sample_autotune chose for this precision and size
+        s.block = t.block;
+        s.unroll = t.unroll;
     }
     const uint64_t groups = (n + s.unroll - 1) / s.unroll;
     const uint64_t need = (groups + s.block - 1) / s.block;
@@ -290,7 +297,7 @@ __global__ void __launch_bounds__(256) fill_kernel(uint64_t n, T *vx, T *vy, T *
 
 hipError_t launch_fill_probe(int mode, uint64_t n, void *vx, void *vy, void *vz, hipStream_t stream)
 {
-    const Shape s = forward_shape(mode, n, true);
+    const Shape s = forward_shape(mode, n, true, false);
     if (mode == kModeF64) {
         hipLaunchKernelGGL((fill_kernel<double, 2>), dim3(s.grid), dim3(s.block), 0, stream, n,
                            static_cast<double *>(vx), static_cast<double *>(vy), static_cast<double *>(vz));

@@ -106,6 +106,52 @@ __device__ __forceinline__ Block4 philox4x32_10_lane(uint64_t pa1, uint32_t u1, 
     return Block4{c0, c1, c2, c3};
 }
 
+// The words a segment's counters (c0, 0, seg, draw) share through Philox's
+// first two rounds: after round 1, c0 = hi(M_B seg) ^ k0 and c1 = lo(M_B seg),
+// and round 2's product M_A c0 (hi, lo).  They depend on seg and the key only,
+// so a batched plan computes them once per segment on the host.
+struct SegWords {
+    uint32_t c0, c1, pa_hi, pa_lo;
+};
+
+// Philox4x32-10 of the counter (c0, 0, seg, draw) from its segment's words:
+// per particle, round 1 takes one product and round 2 one, against two each in
+// philox4x32_10.  The words are the same.
+__device__ __forceinline__ Block4 philox4x32_10_seg(uint32_t c0_in, uint32_t draw, const SegWords &w, uint32_t k0,
+                                                    uint32_t k1)
+{
+    // round 1: M_B seg and the new c0, c1 come from the segment's words
+    const uint64_t pa1 = static_cast<uint64_t>(kMulA) * c0_in;
+    uint32_t c2 = static_cast<uint32_t>(pa1 >> 32) ^ draw ^ k1;
+    uint32_t c3 = static_cast<uint32_t>(pa1);
+    k0 += kWeylA;
+    k1 += kWeylB;
+    uint32_t c0, c1;
+    {  // round 2: M_A c0 is the segment's (pa_hi, pa_lo)
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
+        c0 = xor3(static_cast<uint32_t>(pb >> 32), w.c1, k0);
+        c2 = xor3(w.pa_hi, c3, k1);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = w.pa_lo;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+#pragma unroll
+    for (int r = 2; r < 10; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
+        c1 = static_cast<uint32_t>(pb);
+        c3 = static_cast<uint32_t>(pa);
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
 // Block of particle i (global counter index) in segment seg, draw d.
 __device__ __forceinline__ Block4 particle_block(uint64_t i, uint32_t seg, uint32_t draw, uint32_t k0, uint32_t k1)
 {

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/kappa.h"
 #include "kappa_params.hpp"
 
@@ -27,6 +29,20 @@ struct Shape {
     int grid;
 };
 
+// ---- launch-shape tuning and launch logging (tune.cpp) ---------------------
+enum TunePolicy { kTuneOff = 0, kTuneUse = 1, kTuneRefresh = 2 };
+int autotune_policy();  // KAPPA_AUTOTUNE=off|use|refresh (default use)
+// Shape stored under key in the KAPPA_AUTOTUNE_CACHE file (policy use only).
+bool cache_lookup(const std::string &key, Shape &shape);
+// Records shape under key in the cache file (policies use and refresh).
+void cache_store(const std::string &key, const Shape &shape);
+int size_bucket(uint64_t n);  // smallest b with 2^b >= n
+// Tuned single-species shape for (mode, n's bucket): this process's, else the cache's.
+bool forward_tuned(int mode, uint64_t n, Shape &shape);
+void set_forward_tuned(int mode, uint64_t n, const Shape &shape);
+bool log_enabled();  // KAPPA_LOG set and not "0"
+void log_launch(const char *kernel, int mode, uint64_t n, const Shape &shape, const void *stream);
+
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
@@ -46,9 +62,13 @@ struct FwdArgs {
     SpeciesF32 s32;
 };
 
-// Default shape for n particles in a mode; `vec` selects the vector-store path.
-Shape forward_shape(int mode, uint64_t n, bool vec);
+// Shape for n particles in a mode; `vec` selects the vector-store path.
+// KAPPA_FORWARD_SHAPE overrides it; otherwise, with `tuned`, a shape chosen by
+// kappa_sample_autotune for this precision and size bucket replaces the
+// default (256 threads, 4 particles per thread in FP32 and 2 in FP64).
+Shape forward_shape(int mode, uint64_t n, bool vec, bool tuned = true);
 hipError_t launch_forward(int mode, const Shape &shape, bool vec, const FwdArgs &args, hipStream_t stream);
+uint64_t forward_max_grid();  // workgroups per forward launch (larger calls run in chunks)
 // Unroll (particles per thread) of the default vector-store shape of a mode.
 int forward_default_unroll(int mode);
 // The forward kernel with per-workgroup clock stamps (4 uint64 per workgroup

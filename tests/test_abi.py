@@ -328,3 +328,16 @@ def test_backward_noalloc_argument_checks(monkeypatch):
     assert lib.kappa_sample_backward_noalloc(3.0, 1.0, 1 << 23, 0, 0, 0, 1, FAKE, FAKE, FAKE, FAKE,
                                              None) == _lib.ERANGE
     assert "static scratch" in lib.kappa_last_error().decode()
+
+
+def test_sample_autotune_argument_checks():
+    """kappa_sample_autotune validates before any HIP call."""
+    lib = _lib.load()
+    FAKE = ctypes.c_void_p(0x10000)
+    b, u = ctypes.c_int(), ctypes.c_int()
+    assert lib.kappa_sample_autotune(1, 0, FAKE, FAKE, FAKE, 3, ctypes.byref(b), ctypes.byref(u), None) == _lib.EINVAL
+    assert lib.kappa_sample_autotune(9, 1000, FAKE, FAKE, FAKE, 3, None, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_autotune(1, 1000, FAKE, FAKE, FAKE, 0, None, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_autotune(1, 1000, None, FAKE, FAKE, 3, None, None, None) == _lib.EINVAL
+    assert lib.kappa_sample_autotune(1, 1000, ctypes.c_void_p(0x10004), FAKE, FAKE, 3, None, None,
+                                     None) == _lib.EALIGN
