@@ -579,7 +579,7 @@ def summarise_counters(directory, path, command, mad_per_unit=None, note=None):
     return out
 
 
-def summarise_trace(directory, path, command):
+def summarise_trace(directory, path, command, timed=None):
     """Markdown summary of a rocprofv3 --kernel-trace --runtime-trace run of
     `bench.py --profile-path <path>`: the kernel's durations, the idle gaps
     between consecutive dispatches, and the host time of the HIP launch calls."""
@@ -604,6 +604,18 @@ def summarise_trace(directory, path, command):
              f"| idle gap to the next dispatch | {med(gaps) / 1e3:.2f} | {mean(gaps) / 1e3:.2f} | {gaps[0] / 1e3:.2f} | "
              f"{gaps[-1] / 1e3:.2f} |" if gaps else "| idle gap | - | - | - | - |",
              f"| dispatch period (start to start) | | {period / 1e3:.2f} | | |", ""]
+    if timed:
+        last = [e - b for b, e in zip(st[-timed:], en[-timed:])]
+        lines += [f"The timed region's {timed} dispatches (the last ones of the kernel): mean duration "
+                  f"{sum(last) / len(last) / 1e3:.2f} us.", ""]
+    stats = _rocprof_rows(directory, "kernel_stats.csv")
+    if stats:
+        lines += ["All kernels of the run (kernel_stats.csv):", "", "| Kernel | Calls | Average us | Min us | Max us | % of GPU time |",
+                  "|---|---|---|---|---|---|"]
+        for r in stats:
+            lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+        lines.append("")
     calls = [n for n in ("hipGraphLaunch", "hipLaunchKernel", "hipModuleLaunchKernel", "hipExtLaunchKernel") if n in api]
     if calls:
         lines += ["Host time of the launch calls (hip_api_stats.csv):", "", "| Call | Calls | Average us |", "|---|---|---|"]
@@ -739,6 +751,8 @@ def main():
     ap.add_argument("--mad-per-unit", type=float, default=None,
                     help="with --summarise of a VALU pass: v_mad_u64_u32 per particle from the kernel's ISA")
     ap.add_argument("--note", default=None, help="with --summarise: a note recorded with the summary")
+    ap.add_argument("--timed-dispatches", type=int, default=None,
+                    help="with --summarise of a kernel trace: how many of the last dispatches the timed region holds")
     args = ap.parse_args()
     if args.summarise:
         if not args.profile_path:
@@ -747,7 +761,7 @@ def main():
             print(json.dumps(summarise_counters(args.summarise, args.profile_path, args.command, args.mad_per_unit,
                                                 args.note), indent=1))
         else:
-            print(summarise_trace(args.summarise, args.profile_path, args.command))
+            print(summarise_trace(args.summarise, args.profile_path, args.command, args.timed_dispatches))
         return
     if args.profile_path:
         if args.gpus != 1:

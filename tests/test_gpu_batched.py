@@ -171,3 +171,39 @@ def test_maximum_segment_count():
         s = int(s)
         v = kp.sample(table["kappa"][s], table["theta"][s], 1, 6, seg_id=s, precision=kp.FP32)
         assert bits_equal(tuple(h[s:s + 1] for h in host), to_host(*v)), s
+
+
+def test_segment_longer_than_2_to_32_particles(orc):
+    """A segment of 2^32 + 777 particles between two short ones: the plan splits
+    it into pieces at the counter's 2^32 boundary.  Around that boundary (and at
+    the segment's ends) the plan's output must equal a single-species call over
+    the same counters bit for bit, and the oracle at sampled particles.  The
+    FP32 outputs take 3 x 17.2 GB."""
+    big = (1 << 32) + 777
+    segs = [dict(kappa=2.5, theta=1.1, drift=(0.0, 0.0, 0.0), count=1000, seg_id=7),
+            dict(kappa=3.5, theta=0.9, drift=(0.0, 0.0, 0.0), count=big, seg_id=8),
+            dict(kappa=6.0, theta=1.3, drift=(0.0, 0.0, 0.0), count=5, seg_id=9)]
+    seed = 21
+    with kp.Plan(segs, seed, kp.FP32) as plan:
+        assert plan.total == 1000 + big + 5
+        out = plan.outputs()
+        plan.launch(out)
+        torch.cuda.synchronize()
+        first = 1000  # output position of the big segment's particle 0
+        for lo in (0, (1 << 32) - 40, big - 40):
+            n = 80 if lo + 80 <= big else big - lo
+            ref = kp.sample(3.5, 0.9, n, seed, counter_offset=lo, seg_id=8, precision=kp.FP32)
+            got = tuple(t[first + lo:first + lo + n] for t in out)
+            assert bits_equal(to_host(*got), to_host(*ref)), lo
+        idx = np.array([0, 1, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, big - 1], dtype=np.uint64)
+        r = orc.sample_indices(3.5, 0.9, idx, seed, seg=8, mode=1)
+        it = torch.from_numpy(idx.astype(np.int64) + first).cuda()
+        g = to_host(*(t[it] for t in out))
+        assert norm_rel_err(g, r) <= TOL_FP32
+        # the neighbours are intact
+        for s, pos in ((segs[0], 0), (segs[2], first + big)):
+            ref = kp.sample(s["kappa"], s["theta"], s["count"], seed, seg_id=s["seg_id"], precision=kp.FP32)
+            got = tuple(t[pos:pos + s["count"]] for t in out)
+            assert bits_equal(to_host(*got), to_host(*ref))
+        del out
+    torch.cuda.empty_cache()
