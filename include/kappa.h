@@ -369,6 +369,23 @@ KAPPA_API kappa_status kappa_speed_histogram(const void *vx, const void *vy, con
                                              double theta, double bin_width, uint32_t nbins, uint64_t *counts,
                                              void *stream);
 
+/* kappa_relative_entropy -- the Monte Carlo relative entropy of the second
+ * test (Sec. 5, eq:KL) from a speed histogram of kappa_speed_histogram:
+ *   D = sum_i (P_i + eps) ln((P_i + eps) / (Q_i + eps)),
+ * P_i the exact probability of bin i of the Kappa distribution (the
+ * difference of eq:CDF, the regularized incomplete beta function
+ * I_{x/(x+kappa)}(3/2, kappa - 1/2) with x = (v/theta)^2, at the bin's edges
+ * k w and (k+1) w in units of theta; the last bin, i = nbins, is open-ended;
+ * kappa = +INFINITY takes the Maxwell CDF P(3/2, x)), Q_i = counts[i] over the
+ * sum of the counts.  The paper uses eps = 1e-10.  Host computation.
+ *   counts  host array of nbins + 1 counts (not all zero, else KAPPA_EINVAL)
+ *   D       host, written
+ *   prob    host array of nbins + 1 doubles receiving P_i, or NULL
+ * 1 <= nbins <= 2047 (else KAPPA_ERANGE); bin_width positive and finite,
+ * eps finite and >= 0 (else KAPPA_EINVAL).  No HIP call. */
+KAPPA_API kappa_status kappa_relative_entropy(double kappa, const uint64_t *counts, uint32_t nbins, double bin_width,
+                                              double eps, double *D, double *prob);
+
 /* kappa_divergence_grid -- quality of the approximation G (Sec. 3, eq:G)
  * against the Kappa distribution over a grid of (kappa, c), as in the grid
  * search behind eq:c (Sec. 3, eq:relative_entropy, Fig. fig:map) and the

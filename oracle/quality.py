@@ -19,6 +19,10 @@ the golden-file script beside them and the benchmark's CPU leg may use it.
                           energies in units of m theta^2 / 2 so that
                           E = int x f(x) dx = 3 kappa / (2 kappa - 3)
 
+* F(x; kappa)             Sec. 2, eq:CDF, the speed CDF (regularized
+                          incomplete beta), and the binned relative entropy
+                          D(P||Q) of the second test, Sec. 5, eq:KL
+
 The integrals use mpmath's tanh-sinh quadrature on [0, inf) split at powers
 of ten.  Where the printed formulas contain 1 - (1 + y)^(-k) or (1 + y)^p with
 tiny y, they are evaluated as -expm1(-k log1p(y)) and exp(p log1p(y)): the
@@ -168,3 +172,41 @@ def _golden(fn, lo, hi, tol):
 def quality(kappa, c=None):
     """(D, dE/E) as Python floats."""
     return float(relative_entropy(kappa, c)), float(energy_error(kappa, c))
+
+
+def speed_cdf(kappa, x):
+    """(F, 1 - F) of the speed in x = (v/theta)^2: eq:CDF, the regularized
+    incomplete beta function I_{x/(x+kappa)}(3/2, kappa - 1/2), each side
+    evaluated directly; for kappa = inf the Maxwell CDF P(3/2, x)."""
+    with mp.workdps(DPS):
+        k, x = mp.mpf(kappa), mp.mpf(x)
+        if mp.isinf(k):
+            F = mp.gammainc(mp.mpf(3) / 2, 0, x, regularized=True)
+            R = mp.gammainc(mp.mpf(3) / 2, x, mp.inf, regularized=True)
+        else:
+            F = mp.betainc(mp.mpf(3) / 2, k - mp.mpf(1) / 2, 0, x / (x + k), regularized=True)
+            R = mp.betainc(k - mp.mpf(1) / 2, mp.mpf(3) / 2, 0, k / (x + k), regularized=True)
+        return F, R
+
+
+def binned_relative_entropy(kappa, counts, bin_width, eps):
+    """The Monte Carlo relative entropy of the second test (Sec. 5, eq:KL):
+    sum_i (P_i + eps) ln((P_i + eps) / (Q_i + eps)), P_i the exact probability
+    of speed bin [i w, (i+1) w) in units of theta (the last of len(counts)
+    bins open-ended), Q_i = counts_i / sum(counts).  Returns (D, [P_i])."""
+    with mp.workdps(DPS):
+        n = len(counts)
+        total = mp.fsum(mp.mpf(int(c)) for c in counts)
+        w = mp.mpf(bin_width)
+        P = []
+        F0, R0 = mp.mpf(0), mp.mpf(1)
+        for i in range(n):
+            if i < n - 1:
+                F1, R1 = speed_cdf(kappa, ((i + 1) * w) ** 2)
+                P.append(F1 - F0 if F1 < mp.mpf(1) / 2 else R0 - R1)
+                F0, R0 = F1, R1
+            else:
+                P.append(R0)
+        e = mp.mpf(eps)
+        D = mp.fsum((p + e) * mp.log((p + e) / (mp.mpf(int(c)) / total + e)) for p, c in zip(P, counts))
+        return D, P

@@ -570,29 +570,21 @@ def optimum_c(kappa, c_grid, iters=40, device=None, stream=None):
     return c_opt, d_opt
 
 
-def relative_entropy(kappa, counts, bin_width=0.2, eps=1e-10):
-    """The paper's Monte Carlo relative entropy (eq:KL):
-    D(P||Q) = sum_i (P_i + eps) ln((P_i + eps) / (Q_i + eps)), with P_i the
-    exact Kappa probability of speed bin i (bins of width bin_width in units
-    of theta, the last one open-ended) and Q_i the fraction of the counts.
-    P_i is the difference of the exact CDF of eq:CDF at the bin edges, which is
-    the integral of eq:kappax over the bin; for kappa = inf (Maxwell) it is
-    the regularized incomplete gamma P(3/2, x).  Host-side post-processing of
-    the nbins + 1 counts (scipy's special functions)."""
-    import math
-
+def relative_entropy(kappa, counts, bin_width=0.2, eps=1e-10, with_probabilities=False):
+    """The paper's Monte Carlo relative entropy (eq:KL) of a speed histogram
+    (nbins + 1 counts, the last bin open-ended; a torch tensor or any array)
+    through kappa_relative_entropy: D(P||Q) = sum_i (P_i + eps) ln((P_i + eps)
+    / (Q_i + eps)), P_i the exact Kappa probability of speed bin i (width
+    bin_width in units of theta), Q_i the fraction of the counts.  With
+    with_probabilities, returns (D, P) with P the exact bin probabilities."""
     import numpy as np
-    from scipy import special
-    c = counts.detach().cpu().numpy().astype(np.float64) if hasattr(counts, "detach") else np.asarray(counts, float)
+    c = counts.detach().cpu().numpy() if hasattr(counts, "detach") else np.asarray(counts)
+    c = np.ascontiguousarray(np.rint(c).astype(np.uint64) if c.dtype.kind == "f" else c.astype(np.uint64))
     nb = c.size - 1
-    x = (np.arange(nb + 1) * bin_width) ** 2
-    p = np.empty(nb + 1)
-    if math.isinf(kappa):
-        p[:nb] = np.diff(special.gammainc(1.5, x))
-        p[nb] = special.gammaincc(1.5, x[-1])
-    else:
-        cdf = special.betainc(1.5, kappa - 0.5, x / (x + kappa))
-        p[:nb] = np.diff(cdf)
-        p[nb] = special.betainc(kappa - 0.5, 1.5, kappa / (x[-1] + kappa))  # 1 - F at the last edge
-    q = c / c.sum()
-    return float(np.sum((p + eps) * np.log((p + eps) / (q + eps))))
+    d = ctypes.c_double()
+    p = np.empty(nb + 1, dtype=np.float64)
+    _lib.check(_lib.load().kappa_relative_entropy(float(kappa), c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nb,
+                                                  float(bin_width), float(eps), ctypes.byref(d),
+                                                  p.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "kappa_relative_entropy")
+    return (d.value, p) if with_probabilities else d.value

@@ -69,6 +69,7 @@ SIGNATURES = {
                                    _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "kappa_sample_batched": (_st, [ctypes.POINTER(Segment), _u32, _u64, _i, _vp, _vp, _vp, _vp]),
     "kappa_backward_workspace_bytes": (ctypes.c_size_t, [_u64]),
+    "kappa_relative_entropy": (_st, [_d, ctypes.POINTER(_u64), _u32, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "kappa_sample_autotune": (_st, [_i, _u64, _vp, _vp, _vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _vp]),
     "kappa_sample_backward": (_st, [_d, _d, _u64, _u64, _u64, _u32, _i, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "kappa_sample_backward_noalloc": (_st, [_d, _d, _u64, _u64, _u64, _u32, _i, _vp, _vp, _vp, _vp, _vp]),

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkappa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["setup.cpp", "tune.cpp", "api.hip", "forward.hip", "backward.hip", "batched.hip", "baselines.hip", "histogram.hip",
+SOURCES = ["setup.cpp", "tune.cpp", "api.hip", "forward.hip", "backward.hip", "batched.hip", "baselines.hip", "histogram.hip", "entropy.cpp",
            "divergence.hip", "hwprobe.hip"]
 ARCH = "gfx950"
 

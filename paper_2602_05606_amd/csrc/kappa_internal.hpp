@@ -122,6 +122,10 @@ size_t histogram_lds_bytes(int mode, uint32_t nbins);
 hipError_t launch_histogram(int mode, const void *vx, const void *vy, const void *vz, uint64_t n, double width,
                             uint32_t nbins, uint64_t *counts, hipStream_t stream);
 
+// Speed CDF of the Kappa distribution in x = (v/theta)^2 (eq:CDF; the Maxwell
+// limit for kappa = inf) and its complement, each computed directly (entropy.cpp).
+void speed_cdf(double kappa, double x, double &F, double &one_minus_F);
+
 // ---- approximation quality over (kappa, c) ---------------------------------
 hipError_t launch_optimum(const double *kappa, uint32_t nk, const double *cgrid, uint32_t nc, uint32_t iters,
                           double *c_opt, double *D_opt, hipStream_t stream);
