@@ -70,10 +70,11 @@ void write_cache_file(const char *path, const std::map<std::string, std::string>
     std::rename(tmp.c_str(), path);
 }
 
-// single-species tuned shapes of this process, keyed by forward_tune_key
+// single-species shapes of this process, keyed by forward_tune_key: tuned
+// here, or looked up once in the cache file (grid 0 marks a key the file
+// does not hold), so that a launch reads the file at most once per key
 std::mutex g_fwd_mutex;
 std::map<std::string, Shape> g_fwd_tuned;
-bool g_fwd_any = false;
 
 }  // namespace
 
@@ -131,17 +132,16 @@ std::string forward_tune_key(int mode, uint64_t n)
 bool forward_tuned(int mode, uint64_t n, Shape &shape)
 {
     const std::string key = forward_tune_key(mode, n);
-    {
-        std::lock_guard<std::mutex> lock(g_fwd_mutex);
-        if (g_fwd_any) {
-            const auto it = g_fwd_tuned.find(key);
-            if (it != g_fwd_tuned.end()) {
-                shape = it->second;
-                return true;
-            }
-        }
+    std::lock_guard<std::mutex> lock(g_fwd_mutex);
+    auto it = g_fwd_tuned.find(key);
+    if (it == g_fwd_tuned.end()) {
+        Shape s{0, 0, 0};
+        if (!cache_lookup(key, s)) s = Shape{0, 0, 0};
+        it = g_fwd_tuned.emplace(key, Shape{s.block, s.unroll, s.block > 0 ? 1 : 0}).first;
     }
-    return cache_lookup(key, shape);
+    if (it->second.grid == 0) return false;
+    shape = it->second;
+    return true;
 }
 
 void set_forward_tuned(int mode, uint64_t n, const Shape &shape)
@@ -149,8 +149,7 @@ void set_forward_tuned(int mode, uint64_t n, const Shape &shape)
     const std::string key = forward_tune_key(mode, n);
     {
         std::lock_guard<std::mutex> lock(g_fwd_mutex);
-        g_fwd_tuned[key] = shape;
-        g_fwd_any = true;
+        g_fwd_tuned[key] = Shape{shape.block, shape.unroll, 1};
     }
     cache_store(key, shape);
 }
