@@ -928,7 +928,7 @@ def main():
         g = torch.randn((3, c3["n"]), generator=gen, device=dev, dtype=torch.float32)
         ws = torch.empty(kp.backward_workspace_bytes(c3["n"]), dtype=torch.uint8, device=dev)
         bw_ms = time_launches(lambda: kp.sample_backward(c3["kappa"], c3["theta"], c3["n"], c3["seed"], g[0], g[1],
-                                                         g[2], precision=kp.FP32, workspace=ws), 20, torch)
+                                                         g[2], precision=kp.FP32, workspace=ws), 30, torch, warm=10)
         extras["backward_c3"] = {"particles_per_s": c3["n"] / (bw_ms * 1e-3), "ms": bw_ms,
                                  "GB_per_s_read": 12 * c3["n"] / (bw_ms * 1e-3) / 1e9}
         path_ms["c3-fp32"] = (c3["n"], bw_ms)
@@ -936,7 +936,8 @@ def main():
         g64 = g.double()
         del g
         bw64_ms = time_launches(lambda: kp.sample_backward(c3["kappa"], c3["theta"], c3["n"], c3["seed"], g64[0],
-                                                           g64[1], g64[2], precision=kp.FP64, workspace=ws), 10, torch)
+                                                           g64[1], g64[2], precision=kp.FP64, workspace=ws), 20, torch,
+                                 warm=5)
         extras["backward_c3"]["fp64"] = {"particles_per_s": c3["n"] / (bw64_ms * 1e-3), "ms": bw64_ms,
                                          "GB_per_s_read": 24 * c3["n"] / (bw64_ms * 1e-3) / 1e9}
         path_ms["c3-fp64"] = (c3["n"], bw64_ms)

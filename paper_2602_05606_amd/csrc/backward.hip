@@ -70,13 +70,21 @@ __device__ __forceinline__ void load_group(const T *p, T (&v)[U])
     }
 }
 
-// d(v . g)/dkappa contribution in FP64 for one particle (FP64 mode, FP32 tail).
-__device__ __forceinline__ double dk_term_f64(const InvF64 &inv, const SpeciesF64 &s, double vg)
+// dP/dkappa at the root x of P (eq:v differentiated at fixed U1), in FP64:
+// b' x^2 + (a' + c' L + c L') x + L' with L' = z e^z - expm1(z).
+__device__ __forceinline__ double dP_dkappa_f64(const InvF64 &inv, const SpeciesF64 &s, double x)
 {
-    const double dL = fma(inv.z, inv.ez, -inv.em1);  // z e^z - expm1(z)
-    const double x = inv.x();
-    const double num = fma(s.db * x, x, fma(fma(s.dc, inv.L, s.da) + s.c * dL, x, dL));
-    return vg * (-num / inv.D) / (2.0 * x);
+    const double dL = fma(inv.z, inv.ez, -inv.em1);
+    return fma(fma(s.db, x, fma(s.c, dL, fma(s.dc, inv.L, s.da))), x, dL);
+}
+
+// 1/a for a positive normal a: the hardware estimate and two Newton steps
+// (the error of the estimate squares with each step), within an ulp or two.
+__device__ __forceinline__ double rcp_pos_f64(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+    y = fma(y, fma(-a, y, 1.0), y);
+    return fma(y, fma(-a, y, 1.0), y);
 }
 
 // dL/dkappa at fixed U1 in FP32: z e^z - expm1(z), z = w ln 2.  For z < 1/2
@@ -117,7 +125,15 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
     const T *gx = static_cast<const T *>(a.gx);
     const T *gy = static_cast<const T *>(a.gy);
     const T *gz = static_cast<const T *>(a.gz);
-    double acc_k = 0.0, acc_s = 0.0;
+    // Per particle, with sx = V / theta, g.d the upstream gradient along the
+    // direction and dx/dkappa = -dP/dkappa / D: d(g.v)/dtheta = sx (g.d) and
+    // d(g.v)/dkappa = -(theta / 2) (g.d) (dP/dkappa) / (sx D).  sum_s and sum_k
+    // add sx (g.d) and (g.d) (dP/dkappa) / (sx D); their factors theta and
+    // -theta/2 are applied once per thread.  acc_s and acc_k take theta times
+    // dLoss/dtheta and dLoss/dkappa directly (the FP32 mode's FP64-tail
+    // particles, and the block sums).
+    double acc_k = 0.0, acc_s = 0.0, sum_k = 0.0, sum_s = 0.0;
+    const float neg_dc_kstar = static_cast<float>(-a.s64.dc * a.s64.kstar);  // dc L = -dc kappa* expm1(z)
     const uint64_t ngroups = (a.n + U - 1) / U;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
@@ -149,10 +165,10 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                 speed_uniform_f64(b.r0, b.r3, high, u);
                 const InvF64 inv = invert_f64(high, u, a.s64);
                 const DirF64 d = direction_f64(b.r1, b.r2);
-                const double V = a.s64.theta * inv.sqrt_x();
-                const double vg = V * (d.cx * ux[k] + d.cy * uy[k] + d.cz * uz[k]);
-                acc_s += vg;
-                acc_k += dk_term_f64(inv, a.s64, vg);
+                const double sx = inv.sqrt_x();
+                const double gd = fma(d.cz, uz[k], fma(d.cy, uy[k], d.cx * ux[k]));
+                sum_s = fma(sx, gd, sum_s);
+                sum_k = fma(gd * dP_dkappa_f64(inv, a.s64, sx * sx), rcp_pos_f64(sx * inv.D), sum_k);
             } else {
                 bool high;
                 float y1, d1;
@@ -166,19 +182,18 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                 const bool tail = MODE == kModeF32 && in_fp64_tail(b.r0);
                 tail_dot[k] = dot;
                 tails |= static_cast<uint32_t>(tail) << k;
-                const float sx = inv.sqrt_x();  // V / theta
+                const float sx = inv.sqrt_x();
                 const float x = sx * sx;
-                const float vg = a.s32.theta * sx * dot;
                 const float dL = dL_dkappa_f32(inv);
-                const float num = fmaf(a.s32.db * x, x, fmaf(fmaf(a.s32.dc, inv.L, a.s32.da) + a.s32.c * dL, x, dL));
-                const float term = -vg * num * __builtin_amdgcn_rcpf(2.0f * x * inv.D);
-                grp_s += tail ? 0.0f : vg;
-                grp_k += tail ? 0.0f : term;
+                const float dP = fmaf(fmaf(a.s32.db, x, fmaf(a.s32.c, dL, fmaf(neg_dc_kstar, inv.em1, a.s32.da))), x, dL);
+                const float gd = tail ? 0.0f : dot;
+                grp_s = fmaf(sx, gd, grp_s);
+                grp_k = fmaf(gd * dP, __builtin_amdgcn_rcpf(sx * inv.D), grp_k);
             }
         }
         if constexpr (MODE != kModeF64) {
-            acc_s += static_cast<double>(grp_s);
-            acc_k += static_cast<double>(grp_k);
+            sum_s += static_cast<double>(grp_s);
+            sum_k += static_cast<double>(grp_k);
         }
         if constexpr (MODE == kModeF32) {
             // rare: 1 - U1 < 2^-20, the speed comes from the FP64 inversion
@@ -191,16 +206,20 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
                         double u64;
                         speed_uniform_f64(b.r0, b.r3, h64, u64);
                         const InvF64 i64 = invert_f64(h64, u64, a.s64);
+                        const double sx = i64.sqrt_x();
+                        const double x = sx * sx;
                         // the sampler's output speed is the FP64 speed rounded to float
-                        const double V = static_cast<double>(static_cast<float>(a.s64.theta * i64.sqrt_x()));
+                        const double V = static_cast<double>(static_cast<float>(a.s64.theta * sx));
                         const double vg = V * static_cast<double>(tail_dot[k]);
                         acc_s += vg;
-                        acc_k += dk_term_f64(i64, a.s64, vg);
+                        acc_k -= 0.5 * vg * dP_dkappa_f64(i64, a.s64, x) / (x * i64.D);
                     }
                 }
             }
         }
     }
+    acc_s = fma(sum_s, a.s64.theta, acc_s);
+    acc_k = fma(sum_k, -0.5 * a.s64.theta, acc_k);
     // block reduction: waves, then LDS across the 4 waves, in a fixed order
     __shared__ double red[2][kBwdBlock / 64];
     acc_k = wave_sum(acc_k);
@@ -222,30 +241,49 @@ __global__ void __launch_bounds__(kBwdBlock) backward_kernel(BwdArgs a)
     }
 }
 
-constexpr int kFinBlock = 1024;
+constexpr int kFinBlock = 256;
+constexpr int kFinBatch = kBwdMaxGrid / kFinBlock;  // partial pairs per thread in one pass of the default grid
 
+// Adds the per-block partial pairs in a fixed order: each thread loads a batch
+// of kFinBatch pairs (all loads in flight together) and sums them in index
+// order, then the waves and the 4 waves of the block are summed as in the
+// main kernel.
 __global__ void __launch_bounds__(kFinBlock) backward_finalize(const double *partials, int nblocks,
                                                                double inv_theta, double *grad)
 {
     double sk = 0.0, ss = 0.0;
-    for (int j = threadIdx.x; j < nblocks; j += kFinBlock) {
-        sk += partials[2 * j];
-        ss += partials[2 * j + 1];
-    }
-    __shared__ double red[2][kFinBlock];
-    red[0][threadIdx.x] = sk;
-    red[1][threadIdx.x] = ss;
-    __syncthreads();
-    for (int w = kFinBlock / 2; w > 0; w >>= 1) {
-        if (static_cast<int>(threadIdx.x) < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    for (int base = 0; base < nblocks; base += kFinBlock * kFinBatch) {
+        double pk[kFinBatch], ps[kFinBatch];
+#pragma unroll
+        for (int i = 0; i < kFinBatch; ++i) {
+            const int j = base + i * kFinBlock + static_cast<int>(threadIdx.x);
+            const bool in = j < nblocks;
+            pk[i] = in ? partials[2 * j] : 0.0;
+            ps[i] = in ? partials[2 * j + 1] : 0.0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kFinBatch; ++i) {
+            sk += pk[i];
+            ss += ps[i];
+        }
     }
+    __shared__ double red[2][kFinBlock / 64];
+    sk = wave_sum(sk);
+    ss = wave_sum(ss);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = sk;
+        red[1][wave] = ss;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        grad[0] = red[0][0];
-        grad[1] = red[1][0] * inv_theta;
+        double tk = 0.0, ts = 0.0;
+        for (int w = 0; w < kFinBlock / 64; ++w) {
+            tk += red[0][w];
+            ts += red[1][w];
+        }
+        grad[0] = tk;
+        grad[1] = ts * inv_theta;
     }
 }
 
