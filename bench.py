@@ -29,11 +29,11 @@ METRIC = "particles/sec (3D velocities) and % HBM-write roofline vs same-GPU exa
 # product instantiation, the algorithmic HBM bytes per unit (particle), the
 # direction of that traffic, and the file stem of its profiles under profiles/.
 _FWD = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/forward.hip",
-        "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+        "paper_2602_05606_amd/csrc/kappa_params.hpp", "paper_2602_05606_amd/csrc/kappa_store.hpp"]
 _BWD = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/backward.hip",
         "paper_2602_05606_amd/csrc/kappa_params.hpp"]
 _BAT = ["paper_2602_05606_amd/csrc/kappa_device.hpp", "paper_2602_05606_amd/csrc/batched.hip",
-        "paper_2602_05606_amd/csrc/kappa_params.hpp"]
+        "paper_2602_05606_amd/csrc/kappa_params.hpp", "paper_2602_05606_amd/csrc/kappa_store.hpp"]
 KERNELS = {
     "c2-fp32": dict(stem="forward_fp32_c2", match="forward_kernel<1, 4, true, false>", sources=_FWD, unit_bytes=12,
                     traffic="write", label="forward_kernel<FP32 tail, 4 particles/thread>"),
@@ -49,6 +49,7 @@ KERNELS = {
                    traffic="write", label="batched_kernel<FP32 tail, positions, 4 particles/thread>"),
 }
 KERNELS["c4-graph"] = dict(KERNELS["c4-direct"])
+KERNELS["c4-caller-graph"] = dict(KERNELS["c4-direct"])
 # VALU issue capacity: 256 CUs x 4 SIMDs, 2.4 GHz at most.  Issue floor of one
 # wave64 instruction in SIMD-cycles, from the chip's published vector rates:
 # full-rate 32-bit operations 2 (64 lanes at 32 per cycle: the 157.3 TFLOP/s

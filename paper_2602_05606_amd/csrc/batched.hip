@@ -384,8 +384,8 @@ Shape effective_shape(const kappa_plan_s *p, const Outputs &o)
 
 void drop_graph(kappa_plan_s *p)
 {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
 }
@@ -483,7 +483,7 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
     std::memcpy(host.data() + o_words, words.data(), words.size() * sizeof(SegWords));
     st = check_hip(hipMemcpy(p->dev_block, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy plan tables");
     if (st != KAPPA_OK) {
-        hipFree(p->dev_block);
+        (void)hipFree(p->dev_block);
         delete p;
         return st;
     }
@@ -636,10 +636,11 @@ extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell
         kappa_status st = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
         if (st != KAPPA_OK) return st;
         drop_graph(p);
-        hipFree(p->cell_block);
+        st = check_hip(hipFree(p->cell_block), "hipFree cell table");
         p->cell_block = nullptr;
         p->cell32 = nullptr;
         p->cell64 = nullptr;
+        if (st != KAPPA_OK) return st;
     }
     if (!cells) return KAPPA_OK;
     for (uint32_t s = 0; s < p->nseg; ++s)
@@ -685,7 +686,7 @@ extern "C" kappa_status kappa_plan_set_cells_impl(kappa_plan p, const kappa_cell
     kappa_status st = check_hip(hipMemcpy(p->cell_block, host.data(), bytes, hipMemcpyHostToDevice),
                                 "hipMemcpy cell table");
     if (st != KAPPA_OK) {
-        hipFree(p->cell_block);
+        (void)hipFree(p->cell_block);
         p->cell_block = nullptr;
         return st;
     }
@@ -706,7 +707,7 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
     if (s != KAPPA_OK) return s;
     s = check_hip(hipEventCreate(&e1), "hipEventCreate");
     if (s != KAPPA_OK) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return s;
     }
     const int cus = device_cu_count();
@@ -729,13 +730,14 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
                     s = check_hip(err, "autotune launch");
                     goto done;
                 }
-                hipEventRecord(e0, st);
-                for (int r = 0; r < reps; ++r) launch_batched(p->mode, cand, a, st);
-                hipEventRecord(e1, st);
-                s = check_hip(hipEventSynchronize(e1), "autotune synchronize");
-                if (s != KAPPA_OK) goto done;
+                err = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_batched(p->mode, cand, a, st);
+                if (err == hipSuccess) err = hipEventRecord(e1, st);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                s = check_hip(err, "autotune timing");
+                if (s != KAPPA_OK) goto done;
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = cand;
@@ -744,8 +746,8 @@ extern "C" kappa_status kappa_plan_autotune_impl(kappa_plan p, void *vx, void *v
     p->shape = best;
     cache_store(cache_key(p->mode, p->total, p->nseg), best);
 done:
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return s;
 }
 
@@ -777,9 +779,9 @@ extern "C" kappa_status kappa_plan_destroy_impl(kappa_plan p)
     // launches of this plan may still be in flight on any stream
     (void)hipDeviceSynchronize();
     drop_graph(p);
-    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
-    if (p->dev_block) hipFree(p->dev_block);
-    if (p->cell_block) hipFree(p->cell_block);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->dev_block) (void)hipFree(p->dev_block);
+    if (p->cell_block) (void)hipFree(p->cell_block);
     delete p;
     return KAPPA_OK;
 }
