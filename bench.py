@@ -596,7 +596,7 @@ def summarise_trace(directory, path, command, timed=None):
     period = (st[-1] - st[0]) / (len(st) - 1) if len(st) > 1 else float("nan")
     api = {r["Name"]: r for r in _rocprof_rows(directory, "hip_api_stats.csv")}
     lines = [f"# Kernel trace of `bench.py --profile-path {path}` on MI355X", "",
-             "Command (from the repository root on the GPU box):", "", f"    {command}", "",
+             "Command (from the repository root, on the machine with the GPU):", "", f"    {command}", "",
              f"Kernel `{rows[0]['Kernel_Name'] if rows else k['match']}`: {len(rows)} dispatches "
              "(warm-up included).  Times in microseconds.", "",
              "| Quantity | Median | Mean | Min | Max |", "|---|---|---|---|---|",

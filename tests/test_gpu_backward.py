@@ -100,3 +100,22 @@ def test_autograd_function(orc):
     ref = orc.backward(3.0, 1.2, n, 13, *g, mode=0)
     assert abs(kappa.grad.item() / ref[0] - 1) < 1e-9
     assert abs(theta.grad.item() / ref[1] - 1) < 1e-9
+
+
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
+def test_grid_override_changes_only_the_summation_order(orc, monkeypatch, precision):
+    """KAPPA_BACKWARD_GRID changes the workgroup count and so the order of the
+    FP64 sums, nothing else.  2^23 particles: one thread per group gives 8192
+    partial pairs and 5000 gives a ragged second batch, so the final kernel
+    takes more than one pass over the partials; one workgroup gives one."""
+    n = 1 << 23
+    g = workloads.upstream_gradient(n, seed=23)
+    ref = orc.backward(2.5, 1.3, n, 6, *g, mode=MODE[precision])
+    base = gpu_grad(2.5, 1.3, n, 6, g, precision)
+    tol = 1e-10 if precision == kp.FP64 else 2e-5
+    assert abs(base[0] / ref[0] - 1) < tol and abs(base[1] / ref[1] - 1) < tol
+    for grid in ("0", "5000", "1"):
+        monkeypatch.setenv("KAPPA_BACKWARD_GRID", grid)
+        got = gpu_grad(2.5, 1.3, n, 6, g, precision)
+        for a, b in zip(got, base):
+            assert abs(a - b) <= 1e-12 * (abs(b) + np.sqrt(n)), (grid, got, base)
