@@ -580,7 +580,7 @@ def summarise_counters(directory, path, command, mad_per_unit=None, note=None):
     return out
 
 
-def summarise_trace(directory, path, command, timed=None):
+def summarise_trace(directory, path, command, timed=None, skip=None):
     """Markdown summary of a rocprofv3 --kernel-trace --runtime-trace run of
     `bench.py --profile-path <path>`: the kernel's durations, the idle gaps
     between consecutive dispatches, and the host time of the HIP launch calls."""
@@ -606,9 +606,14 @@ def summarise_trace(directory, path, command, timed=None):
              f"{gaps[-1] / 1e3:.2f} |" if gaps else "| idle gap | - | - | - | - |",
              f"| dispatch period (start to start) | | {period / 1e3:.2f} | | |", ""]
     if timed:
-        last = [e - b for b, e in zip(st[-timed:], en[-timed:])]
-        lines += [f"The timed region's {timed} dispatches (the last ones of the kernel): mean duration "
-                  f"{sum(last) / len(last) / 1e3:.2f} us.", ""]
+        if skip is None:
+            sel, where = slice(-timed, None), "the last ones of the kernel"
+        else:
+            sel, where = slice(skip, skip + timed), f"those after the first {skip}"
+        part = [e - b for b, e in zip(st[sel], en[sel])]
+        span = (en[sel][-1] - st[sel][0]) / len(part) if part else float("nan")
+        lines += [f"The timed region's {timed} dispatches ({where}): mean duration {sum(part) / len(part) / 1e3:.2f} us; "
+                  f"first start to last end {span / 1e3:.2f} us per dispatch.", ""]
     stats = _rocprof_rows(directory, "kernel_stats.csv")
     if stats:
         lines += ["All kernels of the run (kernel_stats.csv):", "", "| Kernel | Calls | Average us | Min us | Max us | % of GPU time |",
@@ -753,7 +758,10 @@ def main():
                     help="with --summarise of a VALU pass: v_mad_u64_u32 per particle from the kernel's ISA")
     ap.add_argument("--note", default=None, help="with --summarise: a note recorded with the summary")
     ap.add_argument("--timed-dispatches", type=int, default=None,
-                    help="with --summarise of a kernel trace: how many of the last dispatches the timed region holds")
+                    help="with --summarise of a kernel trace: how many dispatches the timed region holds (the last "
+                         "ones, or those after --skip-dispatches)")
+    ap.add_argument("--skip-dispatches", type=int, default=None,
+                    help="with --timed-dispatches: dispatches of the kernel before the timed region")
     args = ap.parse_args()
     if args.summarise:
         if not args.profile_path:
@@ -762,7 +770,8 @@ def main():
             print(json.dumps(summarise_counters(args.summarise, args.profile_path, args.command, args.mad_per_unit,
                                                 args.note), indent=1))
         else:
-            print(summarise_trace(args.summarise, args.profile_path, args.command, args.timed_dispatches))
+            print(summarise_trace(args.summarise, args.profile_path, args.command, args.timed_dispatches,
+                                  args.skip_dispatches))
         return
     if args.profile_path:
         if args.gpus != 1:
@@ -806,23 +815,34 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done; timing {args.steps} steps")
-    events = ([], [])
-    step_ev = []
+    # The timed region holds the K steps and one HIP event on each side, on the
+    # stream the library launches on: events recorded between launches cost
+    # about 1.5% of a step, so the per-step and per-launch times of the timing
+    # object come from a second run of steps after the timed one.
+    region = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    region[0].record()
     for _ in range(args.steps):
+        step()
+    region[1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # average launch over the timed region (it includes the short idle gaps between launches)
+    avg_kernel_ms = region[0].elapsed_time(region[1]) / (args.steps * len(kappas))
+    particles = args.steps * len(kappas) * n
+    value = particles / elapsed
+    events = ([], [])
+    step_ev = []
+    for _ in range(max(args.steps, 10)):
         step_ev.append(torch.cuda.Event(enable_timing=True))
         step_ev[-1].record()
         step(events=events)
     step_ev.append(torch.cuda.Event(enable_timing=True))
     step_ev[-1].record()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
     kernel_ms = [s.elapsed_time(e) for s, e in zip(*events)]
-    avg_kernel_ms = sum(kernel_ms) / len(kernel_ms)
     step_ms = [a.elapsed_time(b) for a, b in zip(step_ev[:-1], step_ev[1:])]
-    particles = args.steps * len(kappas) * n
-    value = particles / elapsed
     launch_bytes = 12 * n
     achieved = launch_bytes / (avg_kernel_ms * 1e-3) / 1e9
     log(f"timed: {elapsed * 1e3 / args.steps:.3f} ms/step, {value:.4e} particles/s, kernel {avg_kernel_ms:.4f} ms "
@@ -839,7 +859,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(launch_bytes),
                      "kernel": KERNELS["c2-fp32"]["label"],
                      "algorithmic_bytes_per_launch": launch_bytes, "avg_launch_ms": avg_kernel_ms},
-        "timing": step_protocol(step_ms, len(kappas) * n),
+        "timing": dict(step_protocol(step_ms, len(kappas) * n), launch_ms_mean=sum(kernel_ms) / len(kernel_ms),
+                       how="a second run of steps after the timed one, with HIP events between steps and around "
+                           "each launch"),
     }
     probe = launch_clock_probe(kp, torch, kappas, theta, n, seed, out32)
     result["roofline_alu"] = None  # filled in after the extras, when the stamps are read back

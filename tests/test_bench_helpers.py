@@ -96,6 +96,8 @@ def test_summarise_counters_and_trace(tmp_path):
         w.writerows(rows)
     md = bench.summarise_trace(str(tmp_path / "trace"), "c4-graph", "cmd")
     assert "| kernel duration | 10.00 |" in md and "| idle gap to the next dispatch | 5.00 |" in md
+    md = bench.summarise_trace(str(tmp_path / "trace"), "c4-graph", "cmd", timed=2, skip=1)
+    assert "2 dispatches (those after the first 1): mean duration 10.00 us; first start to last end 12.50 us" in md
 
 
 def test_more_than_one_gpu_is_refused():
