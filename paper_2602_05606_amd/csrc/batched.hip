@@ -43,7 +43,10 @@ namespace kappa {
 
 namespace {
 
-constexpr uint64_t kTile = 1024;  // particles per tile of the segment map
+// Tiles of the segment map: 2^6 particles each, coarser (a power of two) for
+// plans whose map would exceed 2^24 tiles.
+constexpr uint32_t kTileShiftMin = 6;
+constexpr uint64_t kMaxTiles = 1ull << 24;
 
 struct alignas(16) SegF32 {
     float inv_kstar, a, neg_c_kstar, four_b_kstar, two_kstar, two_b, theta, dx, dy, dz;
@@ -66,6 +69,7 @@ struct BatchArgs {
     uint64_t total;
     uint32_t k0, k1;
     uint32_t nseg;
+    uint32_t tile_shift;     // particles per tile: 2^tile_shift
     const uint64_t *start;   // nseg + 1
     const uint32_t *tile;    // ntiles + 1
     const SegF32 *seg32;     // nseg
@@ -142,7 +146,7 @@ __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < ngroups; g += stride) {
         const uint64_t j0 = g * U;
-        const uint64_t t = j0 / kTile;
+        const uint64_t t = j0 >> a.tile_shift;
         uint32_t s = find_segment(a.start, a.tile[t], a.tile[t + 1], j0);
         uint64_t seg_begin = a.start[s], seg_next = a.start[s + 1];  // s + 1 <= nseg
         SegWords wd = a.words[s];
@@ -299,6 +303,7 @@ struct kappa_plan_s {
     void *dev_block = nullptr;  // one allocation holding every table
     const uint64_t *start = nullptr;
     const uint32_t *tile = nullptr;
+    uint32_t tile_shift = kappa::kTileShiftMin;
     const kappa::SegF32 *seg32 = nullptr;
     const kappa::SegF64 *seg64 = nullptr;
     const kappa::SegWords *words = nullptr;
@@ -333,6 +338,7 @@ BatchArgs batch_args(const kappa_plan_s *p, const Outputs &o)
     a.nseg = p->npiece;
     a.start = p->start;
     a.tile = p->tile;
+    a.tile_shift = p->tile_shift;
     a.seg32 = p->seg32;
     a.seg64 = p->seg64;
     a.words = p->words;
@@ -452,12 +458,15 @@ extern "C" kappa_status kappa_plan_create_impl(const kappa_segment *segs, uint32
     p->npiece = npiece;
     start.push_back(acc);
     p->total = acc;
-    const uint64_t ntiles = (acc + kTile - 1) / kTile;
+    uint32_t shift = kTileShiftMin;
+    while ((acc >> shift) >= kMaxTiles) ++shift;
+    p->tile_shift = shift;
+    const uint64_t ntiles = (acc + (1ull << shift) - 1) >> shift;
     std::vector<uint32_t> tile(ntiles + 1);
     {
         uint32_t s = 0;
         for (uint64_t t = 0; t <= ntiles; ++t) {
-            const uint64_t j = std::min<uint64_t>(t * kTile, acc > 0 ? acc - 1 : 0);
+            const uint64_t j = std::min<uint64_t>(t << shift, acc > 0 ? acc - 1 : 0);
             while (s + 1 < npiece && start[s + 1] <= j) ++s;
             tile[t] = s;
         }

@@ -119,3 +119,16 @@ def test_grid_override_changes_only_the_summation_order(orc, monkeypatch, precis
         got = gpu_grad(2.5, 1.3, n, 6, g, precision)
         for a, b in zip(got, base):
             assert abs(a - b) <= 1e-12 * (abs(b) + np.sqrt(n)), (grid, got, base)
+
+
+@pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
+def test_counters_crossing_the_high_word(orc, precision):
+    """A launch whose counters cross 2^32 takes the kernel variant without a
+    shared high counter word; its gradient matches the oracle's."""
+    n, off = 100_003, (1 << 32) - 5000
+    g = workloads.upstream_gradient(n, seed=31)
+    got = gpu_grad(3.0, 1.1, n, 9, g, precision, counter_offset=off)
+    ref = orc.backward(3.0, 1.1, n, 9, *g, counter_offset=off, mode=MODE[precision])
+    tol = 1e-10 if precision == kp.FP64 else 1e-4
+    for a, b in zip(got, ref):
+        assert abs(a - b) <= tol * (abs(b) + np.sqrt(n) * 1e-3), (precision, got, ref)
