@@ -202,13 +202,26 @@ def step_protocol(step_ms, particles_per_step):
     return out
 
 
-def time_launches(fn, reps, torch, warm=2):
+def time_launches(fn, reps, torch, warm=2, warm_ms=50.0):
     """Average duration (ms) of fn() over reps back-to-back calls after `warm`
-    untimed ones: HIP events on the current stream (the one the library
-    launches on) before the first timed call and after the last, so host-side
-    call overhead overlaps the GPU work instead of being counted as idle time."""
+    untimed ones, and more untimed ones until at least warm_ms of GPU time has
+    passed (the core clock ramps up over tens of ms of load after the GPU
+    idles, which it does between the extras): HIP events on the current stream
+    (the one the library launches on) before the first timed call and after
+    the last, so host-side call overhead overlaps the GPU work instead of being
+    counted as idle time."""
+    w0 = torch.cuda.Event(enable_timing=True)
+    w0.record()
     for _ in range(warm):
         fn()
+    while warm_ms > 0:
+        w1 = torch.cuda.Event(enable_timing=True)
+        w1.record()
+        w1.synchronize()
+        if w0.elapsed_time(w1) >= warm_ms:
+            break
+        for _ in range(max(warm, 1)):
+            fn()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record()
@@ -715,7 +728,7 @@ def profile_path(name, steps, warmup, calibrate=False):
     else:
         raise SystemExit(f"unknown profile path {name}; choose from {', '.join(PROFILE_PATHS)}")
     log(f"profile path {name}: {warmup} untimed, {steps} timed calls of {launches} launch(es)")
-    ms = time_launches(fn, steps, torch, warm=warmup) / launches
+    ms = time_launches(fn, steps, torch, warm=warmup, warm_ms=0) / launches
     if calibrate:
         # plain copies of 1.2e9 bytes each way: the scale of the traffic counters
         src = torch.empty(300_000_000, dtype=torch.float32, device=dev)
