@@ -48,6 +48,9 @@ KERNELS = {
     "c4-pic": dict(stem="batched_pic_fp32_c4", match="batched_kernel<1, 4, true>", sources=_BAT, unit_bytes=24,
                    traffic="write", label="batched_kernel<FP32 tail, positions, 4 particles/thread>"),
 }
+KERNELS["hist-fp32"] = dict(stem="histogram_fp32_test2", match="histogram_kernel<float, true>",
+                           sources=["paper_2602_05606_amd/csrc/histogram.hip"], unit_bytes=12, traffic="read",
+                           label="histogram_kernel<float, 16-byte loads>")
 KERNELS["c4-graph"] = dict(KERNELS["c4-direct"])
 KERNELS["c4-caller-graph"] = dict(KERNELS["c4-direct"])
 # VALU issue capacity: 256 CUs x 4 SIMDs, 2.4 GHz at most.  Issue floor of one
@@ -329,6 +332,7 @@ def relative_entropy_test2(kp, torch, dev, kappas=(3.0, 4.1, 7.5), n_max=10 ** 1
         res[str(k)] = row
     h_ms = time_launches(lambda: kp.speed_histogram(*buf, theta=1.0, bin_width=0.2, nbins=100), 5, torch)
     res["histogram_GB_per_s_read"] = 12 * chunk / (h_ms * 1e-3) / 1e9
+    res["histogram_ms"] = h_ms
     return res
 
 
@@ -501,7 +505,7 @@ EXTRAS = ("rates", "simt", "ks", "test2", "survey", "c5", "fp64", "backward", "b
 # launches, W untimed then K timed, so a rocprofv3 trace or counter pass of the
 # command sees that kernel alone (plus torch's own buffer set-up).
 PROFILE_PATHS = ("c1-fp64", "c2-fp32", "c2-fp64", "c3-fp32", "c3-fp64", "c4-direct", "c4-graph", "c4-caller-graph",
-                 "c4-pic", "copy", "store-fp32", "store-fp64", "exact-t", "exact-pareto")
+                 "c4-pic", "hist-fp32", "copy", "store-fp32", "store-fp64", "exact-t", "exact-pareto")
 
 
 def _rocprof_rows(directories, suffix):
@@ -530,6 +534,8 @@ def _path_units(path):
         return workloads.C3["n"]
     if path.startswith("c4"):
         return int(sum(s["count"] for s in workloads.batched_segments()))
+    if path.startswith("hist"):
+        return 10 ** 8
     raise SystemExit(f"no unit count for {path}")
 
 
@@ -720,6 +726,13 @@ def profile_path(name, steps, warmup, calibrate=False):
                     plan.launch(b)
             keep.append((bufs, cg))
             fn, launches = cg.replay, len(bufs)
+    elif name == "hist-fp32":
+        # Test 2's speed histogram of 1e8 FP32 particles (kappa 3), 100 bins of theta/5 and the overflow bin
+        v = kp.sample(3.0, 1.0, 10 ** 8, 1, precision=kp.FP32)
+        counts = torch.zeros(101, dtype=torch.int64, device=dev)
+        keep.append((v, counts))
+        fn = lambda: kp.speed_histogram(*v, theta=1.0, bin_width=0.2, nbins=100, counts=counts)
+        units, unit_bytes = 10 ** 8, 12
     elif name == "copy":
         src = torch.empty(300_000_000, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -926,6 +939,7 @@ def main():
         log("KS distances done")
     if "test2" in chosen:
         extras["relative_entropy_test2"] = relative_entropy_test2(kp, torch, dev)
+        path_ms["hist-fp32"] = (10 ** 8, extras["relative_entropy_test2"]["histogram_ms"])
         log("relative-entropy test done")
     if "survey" in chosen:
         extras["divergence_survey"] = divergence_survey(kp, torch, dev)
