@@ -43,9 +43,9 @@ KERNELS = {
                     traffic="read", label="backward_kernel<FP32 tail, 4 particles/thread>"),
     "c3-fp64": dict(stem="backward_fp64_c3", match="backward_kernel<0, 2, true, true>", sources=_BWD, unit_bytes=24,
                     traffic="read", label="backward_kernel<FP64, 2 particles/thread>"),
-    "c4-direct": dict(stem="batched_fp32_c4", match="batched_kernel<1, 4, false>", sources=_BAT, unit_bytes=12,
+    "c4-direct": dict(stem="batched_fp32_c4", match="batched_kernel<1, 4, false, unsigned int>", sources=_BAT, unit_bytes=12,
                       traffic="write", label="batched_kernel<FP32 tail, 4 particles/thread>"),
-    "c4-pic": dict(stem="batched_pic_fp32_c4", match="batched_kernel<1, 4, true>", sources=_BAT, unit_bytes=24,
+    "c4-pic": dict(stem="batched_pic_fp32_c4", match="batched_kernel<1, 4, true, unsigned int>", sources=_BAT, unit_bytes=24,
                    traffic="write", label="batched_kernel<FP32 tail, positions, 4 particles/thread>"),
 }
 KERNELS["hist-fp32"] = dict(stem="histogram_fp32_test2", match="histogram_kernel<float, true>",

@@ -39,8 +39,8 @@ __device__ __forceinline__ void store_group(T *p, const T (&v)[U])
 
 // The group at element j0 of an array of n: the vector store when the whole
 // group lies inside, one element per store for a ragged last group.
-template <typename T, int U>
-__device__ __forceinline__ void store_or_tail(T *p, uint64_t j0, uint64_t n, const T (&v)[U])
+template <typename T, int U, typename I = uint64_t>
+__device__ __forceinline__ void store_or_tail(T *p, I j0, I n, const T (&v)[U])
 {
     if (j0 + U <= n) {
         store_group<T, U>(p + j0, v);

@@ -88,7 +88,7 @@ def test_summarise_counters_and_trace(tmp_path):
     # kernel trace: two dispatches 10 us long, 5 us apart
     k = tmp_path / "trace" / "h" / "3"
     k.mkdir(parents=True)
-    rows = [{"Kernel_Name": "batched_kernel<1, 4, false>(...)", "Start_Timestamp": s, "End_Timestamp": s + 10_000}
+    rows = [{"Kernel_Name": "batched_kernel<1, 4, false, unsigned int>(...)", "Start_Timestamp": s, "End_Timestamp": s + 10_000}
             for s in (0, 15_000, 30_000)]
     with open(k / "z_kernel_trace.csv", "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=list(rows[0]))
