@@ -95,9 +95,10 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t *start, uint32_t
     return lo;
 }
 
-// A group's U particles usually lie in one segment (C4's segments hold about
-// 420 particles): the segment's bounds, id and setup block are loaded once
-// per group and reloaded only where the group crosses into the next segment.
+// A group's U particles usually lie in one segment (PIC cells hold hundreds of
+// particles per species): the segment's bounds, id and setup block are loaded
+// once per group and reloaded only where the group crosses into the next
+// segment.
 template <int MODE>
 struct SegParams;
 
@@ -138,7 +139,7 @@ struct CellParams<kModeF64> {
 
 // I is the particle index type: uint32_t when the plan holds fewer than 2^31
 // particles and the grid fewer than 2^31 threads (32-bit index arithmetic, 3%
-// faster at C4's size), else uint64_t.
+// faster for 5.1e6 particles in 12,288 segments), else uint64_t.
 template <int MODE, int U, bool POS, typename I>
 __global__ void __launch_bounds__(256) batched_kernel(BatchArgs a)
 {
