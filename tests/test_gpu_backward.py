@@ -38,6 +38,19 @@ def test_c3_full_size_against_oracle_adjoint(orc):
     assert rk < 1e-5 and rt < 1e-5
 
 
+def test_c3_full_size_fp64_against_oracle_adjoint(orc):
+    """C3 in FP64 (the same upstream gradient in double, FP64 inversion):
+    2^26 particles against the oracle's adjoint; only the order of the FP64
+    sums differs."""
+    c = workloads.C3
+    g = workloads.upstream_gradient(c["n"])
+    got = gpu_grad(c["kappa"], c["theta"], c["n"], c["seed"], g, kp.FP64)
+    ref = orc.backward(c["kappa"], c["theta"], c["n"], c["seed"], g[0], g[1], g[2], mode=0)
+    rk, rt = abs(got[0] / ref[0] - 1), abs(got[1] / ref[1] - 1)
+    print(f"C3 FP64 dL/dkappa rel {rk:.2e}, dL/dtheta rel {rt:.2e}")
+    assert rk < 1e-9 and rt < 1e-9
+
+
 @pytest.mark.parametrize("precision", [kp.FP64, kp.FP32])
 @pytest.mark.parametrize("kappa,theta", [(2.5, 1.3), (1.6, 1.0), (4.1, 0.8), (10.0, 2.0)])
 def test_against_finite_differences(orc, precision, kappa, theta):

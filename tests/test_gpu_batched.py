@@ -68,6 +68,23 @@ def test_c4_against_oracle(orc, c4):
     assert worst <= TOL_FP32
 
 
+def test_c4_fp64_against_oracle(orc, c4):
+    """The C4 table in FP64: every particle of every segment against the oracle."""
+    segs, start = c4
+    seed = workloads.C4["seed"]
+    host = to_host(*kp.sample_batched(segs, seed, kp.FP64))
+    worst = 0.0
+    for s, seg in enumerate(segs):
+        n = seg["count"]
+        r = orc.sample(seg["kappa"], seg["theta"], n, seed, seg=seg["seg_id"], mode=0, drift=seg["drift"])[:3]
+        g = tuple(h[start[s]:start[s + 1]] for h in host)
+        d = np.sqrt(sum((a - b) ** 2 for a, b in zip(g, r)))
+        scale = np.sqrt(sum((b - dr) ** 2 for b, dr in zip(r, seg["drift"]))) + np.linalg.norm(seg["drift"])
+        worst = max(worst, float(np.max(d / scale)))
+    print(f"C4 FP64 all {int(start[-1])} particles of {len(segs)} segments: max error {worst:.3e}")
+    assert worst <= TOL_FP64
+
+
 def test_graph_replay_matches_direct_launch(c4):
     segs, _ = c4
     with kp.Plan(segs, 4, kp.FP32) as plan:
