@@ -48,6 +48,13 @@ KERNELS = {
     "c4-pic": dict(stem="batched_pic_fp32_c4", match="batched_kernel<1, 4, true, unsigned int>", sources=_BAT, unit_bytes=24,
                    traffic="write", label="batched_kernel<FP32 tail, positions, 4 particles/thread>"),
 }
+_EXACT = ["paper_2602_05606_amd/csrc/baselines.hip", "paper_2602_05606_amd/csrc/kappa_device.hpp",
+          "paper_2602_05606_amd/csrc/kappa_store.hpp"]
+KERNELS["exact-t"] = dict(stem="exact_t_fp32_c2", match="exact_t_kernel<float, 4, true>", sources=_EXACT, unit_bytes=12,
+                          traffic="write", label="exact_t_kernel<float, 4 particles/thread> (t/gamma rejection)")
+KERNELS["exact-pareto"] = dict(stem="exact_pareto_fp32_c2", match="exact_pareto_kernel<float, 4, true>", sources=_EXACT,
+                               unit_bytes=12, traffic="write",
+                               label="exact_pareto_kernel<float, 4 particles/thread> (Pareto rejection)")
 KERNELS["hist-fp32"] = dict(stem="histogram_fp32_test2", match="histogram_kernel<float, true>",
                            sources=["paper_2602_05606_amd/csrc/histogram.hip"], unit_bytes=12, traffic="read",
                            label="histogram_kernel<float, 16-byte loads>")
@@ -528,7 +535,7 @@ def _rocprof_rows(directories, suffix):
 def _path_units(path):
     sys.path.insert(0, ROOT)
     import workloads
-    if path.startswith("c2"):
+    if path.startswith("c2") or path.startswith("exact"):
         return workloads.C2["n"]
     if path.startswith("c3"):
         return workloads.C3["n"]
